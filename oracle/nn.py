@@ -1,0 +1,89 @@
+"""Oracle of the learned preconditioner network (FP64, test infrastructure).
+
+The network is a local map on the extended lattice: three 3^4-tap
+convolution layers whose taps follow the C* neighbour map, real channels
+24 -> 32 -> 32 -> 24, no biases, ReLU after the first two layers.
+
+* Input: an even-site spinor ``r`` (V, 4, 3) complex, embedded on the whole
+  lattice with the odd sites set to zero, as 24 real channels per site:
+  channel ``2 c + 0`` = Re, ``2 c + 1`` = Im of component ``c = 3 spin + colour``.
+* Output: the 24 channels of the last layer read back as a spinor, kept on the
+  even sites only.
+* Preconditioner use: ``M(r) = |r| N(r / |r|)``.
+* Training loss over a batch: ``mean_i |N(rhat_i) - ehat_i|^2 / |ehat_i|^2``
+  with ``rhat = r / |r|``, ``ehat = e / |r|``.
+
+Weights ``W[l]`` have shape (81, cout, cin); tap = 27(d0+1)+9(d1+1)+3(d2+1)+(d3+1).
+Backward is the chain rule written out layer by layer: the data gradient of
+a convolution is its adjoint (the oracle's literal scatter), the weight
+gradient is the site sum of (output gradient) x (shifted input).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CHANNELS = (24, 32, 32, 24)
+
+
+def embed(o, r):
+    par = o.parity()
+    h = np.zeros((o.V, 24), dtype=np.float64)
+    rr = r.reshape(o.V, 12)
+    h[:, 0::2] = rr.real
+    h[:, 1::2] = rr.imag
+    h[par == 1] = 0.0
+    return h
+
+
+def unembed(o, y):
+    par = o.parity()
+    out = (y[:, 0::2] + 1j * y[:, 1::2]).reshape(o.V, 4, 3).copy()
+    out[par == 1] = 0.0
+    return out
+
+
+def forward(o, W, r):
+    """N(r) and the activations needed by the backward pass."""
+    h0 = embed(o, r)
+    a1 = o.nn_conv(W[0], h0)
+    h1 = np.maximum(a1, 0.0)
+    a2 = o.nn_conv(W[1], h1)
+    h2 = np.maximum(a2, 0.0)
+    a3 = o.nn_conv(W[2], h2)
+    return unembed(o, a3), (h0, a1, h1, a2, h2, a3)
+
+
+def apply_precond(o, W, r):
+    n = np.linalg.norm(r)
+    y, _ = forward(o, W, r / n)
+    return n * y
+
+
+def backward(o, W, acts, gy):
+    """Weight gradients given dL/dy (an even-site spinor)."""
+    h0, a1, h1, a2, h2, a3 = acts
+    g3 = embed(o, gy)
+    dW3 = o.nn_conv_wgrad(g3, h2, 32, 24)
+    g2 = o.nn_conv_adjoint(W[2], g3) * (a2 > 0)
+    dW2 = o.nn_conv_wgrad(g2, h1, 32, 32)
+    g1 = o.nn_conv_adjoint(W[1], g2) * (a1 > 0)
+    dW1 = o.nn_conv_wgrad(g1, h0, 24, 32)
+    return [dW1, dW2, dW3]
+
+
+def loss_and_grad(o, W, rs, es):
+    """Batch loss and its weight gradients; ``rs``, ``es`` are lists of spinors."""
+    B = len(rs)
+    L = 0.0
+    grads = [np.zeros_like(w) for w in W]
+    for r, e in zip(rs, es):
+        n = np.linalg.norm(r)
+        rh, eh = r / n, e / n
+        y, acts = forward(o, W, rh)
+        d = y - eh
+        ne2 = np.vdot(eh, eh).real
+        L += np.vdot(d, d).real / ne2 / B
+        gy = 2.0 * d / ne2 / B
+        for k, g in enumerate(backward(o, W, acts, gy)):
+            grads[k] += g
+    return L, grads
