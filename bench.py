@@ -1,0 +1,236 @@
+"""Benchmark of the Wilson-clover / C* hot path on one MI355X.
+
+Workload (default): the 32^3 x 64 lattice with C* in three directions, i.e. the
+doubled 64 x 64 x 32 x 32 extended lattice (t, x1, x2, x3), two flavours
+(qhat = -2, kappa = 0.136377; qhat = 4, kappa = 0.137312; su3csw 1.90952,
+u1csw 1), seeded synthetic SU(3) x U(1) fields (exp of Gaussian traceless
+anti-Hermitian matrices, sigma 0.2; U(1) angles sigma 0.3).
+
+One step applies the even-odd Schur operator D_hat once per flavour in FP64
+and once in FP32, on in/out buffers rotated over four pairs (so no operand
+stays in the 256 MB last-level cache between applications).  `value` is the
+algorithmic bytes of all those applications divided by the timed wall time.
+Algorithmic bytes of one D_hat application: 552 reals per even site (links read
+once per pass: 288; clover blocks H_e and H_o^-1: 144; spinors: 120).
+
+Extra legs (not part of `value`): the time to a true FP64 residual 1e-10 of FP64
+CG against mixed-precision FGCR (and, when a trained network is available,
+network-preconditioned FGCR) on the same lattice; and the FP64 CPU oracle timed
+on a bounded sample of even sites of the same lattice (`cpu_baseline`).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dw GB/s & %HBM roofline; time-to-1e-10 residual, mixed+learned vs FP64 CG"
+HBM_PEAK_GBS = 8000.0
+REALS_PER_VE = 552
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_fields(w):
+    import synthgen as sg
+    L = w["L"]
+    vphys = L[0] * L[1] * L[2] * L[3]
+    U = sg.gauge_su3(w["gauge_seed"], w["sigma_su3"], vphys)
+    A = sg.gauge_u1(w["gauge_seed"], w["sigma_u1"], vphys)
+    return U, A
+
+
+def cpu_baseline(w, U, A, flav, seconds=15.0):
+    """Oracle D_hat on a bounded sample of even sites of the same lattice."""
+    import oracle
+    import synthgen as sg
+    o = oracle.Oracle(w["L"], w["cstar"])
+    o.set_gauge_physical(U, A)
+    o.set_flavour(**flav, cache=False, blocks=False)
+    psi = sg.spinor(w["source_seed"], o.V)
+    par = o.parity()
+    psi[par == 1] = 0
+    even = np.nonzero(par == 0)[0]
+    rng = np.random.default_rng(0)
+    n = 64
+    done, t_tot = 0, 0.0
+    while t_tot < seconds:
+        sites = rng.choice(even, size=n, replace=False)
+        t0 = time.perf_counter()
+        o.schur_sites(psi, sites)
+        t_tot += time.perf_counter() - t0
+        done += n
+        n = min(2 * n, 4096)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    gbs = done * REALS_PER_VE * 8 / t_tot / 1e9
+    return {"value": gbs, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "%d random even sites of the same lattice (FP64 D_hat, oracle as is), %.1f s" % (done, t_tot)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the multi-GPU path (time-slab halo exchange over xGMI) "
+              "is a design, not part of this build; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1908_11673_amd as qxd
+    import synthgen as sg
+
+    w = sg.WORKLOADS[args.workload]
+    flavours = [sg.FLAVOURS["d"], sg.FLAVOURS["u"]]
+    log("generating %s fields %s" % (args.workload, w["L"]))
+    U, A = make_fields(w)
+    lats = []
+    for f in flavours:
+        lat = qxd.Lattice(w["L"], w["cstar"])
+        st = lat.setup(U, A, f)
+        log("flavour qhat=%d: clover min pivot %.4f" % (f["qhat"], st["min_pivot"]))
+        lats.append(lat)
+    Ve = lats[0].Ve
+    torch.cuda.synchronize()
+
+    nbuf = 4
+    psi = sg.spinor(w["source_seed"], lats[0].V)
+    src64 = lats[0].pack(torch.from_numpy(psi).cuda())
+    src32 = lats[0].pack(torch.from_numpy(psi).cuda(), qxd.F32)
+    ins = {qxd.F64: [], qxd.F32: []}
+    outs = {qxd.F64: [], qxd.F32: []}
+    for i in range(nbuf):
+        for p, src in ((qxd.F64, src64), (qxd.F32, src32)):
+            t = qxd.field(Ve, p)
+            t.copy_(src[:12 * Ve] * (1.0 + 0.01 * i))
+            ins[p].append(t)
+            outs[p].append(qxd.field(Ve, p))
+    del psi
+
+    stream = torch.cuda.current_stream()
+    sptr = stream.cuda_stream
+
+    def step(i):
+        for lat in lats:
+            for p in (qxd.F64, qxd.F32):
+                qxd.qxd_dw_eo_schur(lat.h, p, 0, outs[p][i % nbuf], ins[p][i % nbuf], sptr)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for i in range(args.steps):
+        step(i)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    bytes_step = len(lats) * (REALS_PER_VE * 8 + REALS_PER_VE * 4) * Ve
+    value = bytes_step / (ms_step * 1e-3) / 1e9
+    log("timed %d steps: %.3f ms/step (wall %.3f s)" % (args.steps, ms_step, wall))
+
+    # dominant kernel: FP64 D_hat (two launches: odd-site pass and even-site pass), timed alone
+    n64 = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(n64):
+        qxd.qxd_dw_eo_schur(lats[0].h, qxd.F64, 0, outs[qxd.F64][i % nbuf], ins[qxd.F64][i % nbuf], sptr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms64 = e0.elapsed_time(e1) / n64
+    n32 = 100
+    e0.record(stream)
+    for i in range(n32):
+        qxd.qxd_dw_eo_schur(lats[0].h, qxd.F32, 0, outs[qxd.F32][i % nbuf], ins[qxd.F32][i % nbuf], sptr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1) / n32
+    ach64 = REALS_PER_VE * 8 * Ve / (ms64 * 1e-3) / 1e9
+    ach32 = REALS_PER_VE * 4 * Ve / (ms32 * 1e-3) / 1e9
+    log("D_hat FP64 %.3f ms (%.0f GB/s), FP32 %.3f ms (%.0f GB/s)" % (ms64, ach64, ms32, ach32))
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "D_hat applies, 32^3x64 physical with C* in 3 directions "
+                               "(extended 64x64x32x32), 2 flavours x {FP64, FP32} per step",
+                   "extended_lattice": [w["L"][0], 2 * w["L"][1], w["L"][2], w["L"][3]],
+                   "even_sites": Ve, "flavours": [{"qhat": f["qhat"], "kappa": f["kappa"]} for f in flavours],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(ach64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach64 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "D_hat FP64 (k_schur1 + k_schur2)", "ms_per_launch": round(ms64, 4)},
+        "dhat_fp32": {"ms": round(ms32, 4), "achieved_gbs": round(ach32, 1), "frac": round(ach32 / HBM_PEAK_GBS, 4)},
+    }
+
+    if not args.no_solve:
+        result["time_to_solution"] = solve_leg(qxd, torch, lats, w)
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(w, U, A, flavours[0], args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+    for lat in lats:
+        lat.close()
+
+
+def solve_leg(qxd, torch, lats, w):
+    import synthgen as sg
+    out = {}
+    b = sg.spinor(w["source_seed"] + 1, lats[0].V)
+    for lat, name in zip(lats, ("qhat-2", "qhat+4")):
+        bd = lat.pack(torch.from_numpy(b).cuda())
+        x = lat.field(qxd.F64, full=True)
+        res = {}
+        for tag, fn in (
+                ("cg_f64", lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, check_every=8), x, bd,
+                                                    check=False)),
+                ("fgcr_f32_in_f64", lambda: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32,
+                                                                                        nkv=16), None, x, bd,
+                                                               check=False)),
+                ("fgcr_bf16links_in_f64", lambda: qxd.qxd_solve_fgcr(
+                    lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.BF16, nkv=16), None, x, bd, check=False))):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = fn()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            res[tag] = {"ms": round(ms, 2), "status": st["status"], "iterations": st["inner_it"],
+                        "outer": st["outer_it"], "schur_applies": st["schur_applies"],
+                        "true_residual": st["true_residual"]}
+            log("solve %s %s: %.1f ms, %d it, res %.2e, status %d" % (name, tag, ms, st["inner_it"],
+                                                                       st["true_residual"], st["status"]))
+        out[name] = res
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,252 @@
+/*
+ * qxd.h -- C ABI of libqxd: the Wilson-clover operator with SU(3) x U(1)^qhat
+ * links under C* boundary conditions on MI355X (gfx950), its even-odd Schur
+ * complement, and the Krylov solves built on it (openQ*D, arXiv:1908.11673).
+ *
+ * Paper references are to sections and equations of arXiv:1908.11673:
+ *   Sec. 2.1  C* boundary conditions, the extended (orbifold) lattice
+ *   Sec. 2.3  the Dirac operator: D = m0 + Dw + dD_sw, the covariant
+ *             derivatives with U z^qhat, the SU(3) and U(1) SW terms, and the
+ *             even-odd preconditioned operator D_hat = D_ee - D_eo D_oo^-1 D_oe
+ *   Sec. 4.4  the solvers (CG on D_hat^+ D_hat, GCR) and the residue 1e-10
+ *
+ * Conventions the paper leaves to other documents:
+ *   - chiral gamma basis, 2x2 blocks: g0 = [[0,-1],[-1,0]], gk = [[0,-i s_k],[i s_k,0]],
+ *     gamma5 = diag(1,1,-1,-1); sigma_{mu nu} = (i/2)[g_mu, g_nu];
+ *   - F_{mu nu} = (1/8)(Q_{mu nu} - Q_{mu nu}^+) from the four clover leaves, no
+ *     trace removed; the U(1) tensor is built from unit-charge plaquettes, so the
+ *     SW term carries u1csw * qhat * (i/4) Im(sum of the four z_{mu nu}) and does
+ *     not depend on invqel;
+ *   - the diagonal of D is 1/(2 kappa) (a m0 = 1/(2 kappa) - 4);
+ *   - fermions periodic in time unless t_antiperiodic is set.
+ *
+ * ---------------------------------------------------------------------------
+ * Lattice and layouts
+ *
+ * Physical extents L0 (time), L1, L2, L3, all even and >= 2.  With cstar >= 1
+ * the library works on the extended lattice L0 x 2L1 x L2 x L3 (Sec. 2.1):
+ * direction 1 is periodic with period 2L1, and for 2 <= k <= cstar a hop across
+ * the k boundary also moves x1 by L1.  Canonical site index on the extended
+ * lattice: s = x3 + L3 (x2 + L2 (x1 + L1ext x0)); parity (x0+x1+x2+x3) mod 2;
+ * the half index of a site within its parity is s / 2.  Ve = V / 2.
+ *
+ * Canonical (AoS) spinor: [V][4 spin][3 colour] complex128, interleaved re, im.
+ * Device (SoA even-odd, "eo") spinor of precision p:
+ *   half field (one parity):  F64  [12 components][Ve] complex128
+ *                             F32  [6 pairs][Ve] (2 complex64 per 16 bytes)
+ *                             BF16 [3 quads][Ve] (4 complex bf16 per 16 bytes)
+ *   full field: the even half followed by the odd half.
+ * Component c = 3 spin + colour.  Sizes in bytes: 192 Ve (F64), 96 Ve (F32),
+ * 48 Ve (BF16) per half field.
+ *
+ * Every field pointer is a caller-owned device pointer unless stated.  All
+ * calls are asynchronous on the given HIP stream (a hipStream_t passed as
+ * void*, NULL for the null stream) except where stated; the solvers block
+ * until their statistics are final.  One handle per host thread.
+ *
+ * Errors: every call returns a qxd_status; nothing throws or aborts across the
+ * ABI.  On an error the outputs are unspecified and the handle stays usable.
+ */
+#ifndef QXD_H
+#define QXD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QXD_OK = 0,
+  QXD_EINVAL = 1,     /* bad argument (NULL pointer, size, enum value) */
+  QXD_EGEOM = 2,      /* odd or too small extent, cstar outside 0..3, volume too large */
+  QXD_ENOMEM = 3,     /* device allocation failed */
+  QXD_ESINGULAR = 4,  /* a clover block has |pivot| < 1e-14 |H| */
+  QXD_ENAN = 5,       /* a non-finite value reached a solver reduction */
+  QXD_ENOCONV = 6,    /* the iteration limit was reached before the target */
+  QXD_EHIP = 7,       /* a HIP runtime call failed */
+  QXD_ESTATE = 8      /* call out of order (e.g. apply before clover_invert) */
+} qxd_status;
+
+typedef enum { QXD_F64 = 0, QXD_F32 = 1, QXD_BF16 = 2 } qxd_prec;
+
+typedef struct {
+  int L[4];            /* physical L0 (time), L1, L2, L3: even, >= 2 */
+  int cstar;           /* C* directions 0..3, switched on in 1, 2, 3 order (Sec. 2.1) */
+  int t_antiperiodic;  /* 1: fermion sign -1 on the time wrap */
+} qxd_geom;
+
+typedef struct {
+  int qhat;            /* integer charge q / q_el (Sec. 2.3) */
+  double invqel;       /* 1 / q_el; does not enter the operator (it cancels) */
+  double kappa;        /* hopping parameter, diagonal 1/(2 kappa) */
+  double su3csw;       /* SU(3) SW coefficient */
+  double u1csw;        /* U(1) SW coefficient (1 at tree level) */
+} qxd_flavour;
+
+typedef struct {
+  double min_pivot;    /* smallest |pivot| met in the 6x6 block inversions */
+  double max_norm;     /* largest max-abs entry of a 6x6 block */
+  int64_t n_singular;  /* blocks with |pivot| < 1e-14 max-abs entry */
+} qxd_clover_stats;
+
+typedef enum { QXD_PRECOND_NONE = 0, QXD_PRECOND_NN = 1 } qxd_precond_kind;
+
+typedef struct {
+  int nmx;             /* iteration limit (CG: iterations; FGCR: inner steps in total) */
+  double res;          /* target true relative residual |b - D x| / |b| (full lattice) */
+  int inner_prec;      /* qxd_prec of the inner FGCR operator (F64: no defect correction) */
+  double inner_res;    /* relative residual reduction asked of each inner solve */
+  int nkv;             /* FGCR restart length (1..64) */
+  int max_outer;       /* defect-correction steps limit */
+  int check_every;     /* CG: read the residual back every this many iterations */
+  int fallback_after;  /* NN FGCR: inner steps without progress before dropping M */
+} qxd_solver_params;
+
+typedef struct {
+  int status;          /* qxd_status of the solve */
+  int outer_it;        /* defect-correction steps */
+  int inner_it;        /* CG iterations or FGCR steps, summed */
+  int64_t schur_applies; /* D_hat or D_hat^+ applications, all precisions */
+  int64_t nn_applies;  /* preconditioner network applications */
+  double true_residual;/* FP64 |b - D x| / |b| on the full lattice, recomputed */
+  double t_ms;         /* wall time of the call */
+  int fell_back;       /* 1 if the network preconditioner was dropped */
+} qxd_solver_stats;
+
+typedef struct qxd_handle qxd_handle;
+typedef struct qxd_nn qxd_nn;
+
+/* Status name for printing. */
+const char *qxd_status_string(qxd_status s);
+
+/* Create a handle for the geometry (Sec. 2.1).  Checks extents and cstar on
+ * the host before any allocation: QXD_EGEOM on odd or < 2 extents, cstar
+ * outside 0..3, or an extended volume >= 2^31.  Device: the current one. */
+qxd_status qxd_create(const qxd_geom *g, qxd_handle **h);
+qxd_status qxd_destroy(qxd_handle *h);
+
+/* Extended volume V and Ve = V/2. */
+qxd_status qxd_volume(const qxd_handle *h, int64_t *V, int64_t *Ve);
+
+/* Gauge fields on the physical lattice: U_phys [4][Vphys][3][3] complex128 (row,
+ * column), A_phys [4][Vphys] float64, Vphys = L0 L1 L2 L3, physical site index
+ * x3 + L3 (x2 + L2 (x1 + L1 x0)).  on_device != 0: device pointers, else host
+ * pointers (copied synchronously).  The library keeps its own copy and fills the
+ * mirror half U(x + L1 e1) = U(x)*, A(x + L1 e1) = -A(x) itself (Sec. 2.1). */
+qxd_status qxd_set_gauge(qxd_handle *h, const double *U_phys, const double *A_phys, int on_device, void *stream);
+
+/* Select the flavour and build the combined links V(x,mu) = U(x,mu) z(x,mu)^qhat
+ * (Sec. 2.3, covariant derivatives) on the extended lattice in every storage
+ * precision.  Invalidates the clover until the next clover_build/invert. */
+qxd_status qxd_set_flavour(qxd_handle *h, const qxd_flavour *f, void *stream);
+
+/* SW term (Sec. 2.3): the site-diagonal 1/(2 kappa) + dD_sw on every site, as two
+ * Hermitian 6x6 chirality blocks. */
+qxd_status qxd_clover_build(qxd_handle *h, void *stream);
+
+/* Invert the odd-site blocks (D_oo^-1 in Sec. 2.3's Schur complement) in FP64
+ * by Gauss-Jordan elimination with partial pivoting, and store FP32 copies.
+ * Synchronous (reads the statistics back); QXD_ESINGULAR if any block is
+ * numerically singular. */
+qxd_status qxd_clover_invert(qxd_handle *h, qxd_clover_stats *stats, void *stream);
+
+/* out = D in on the full extended lattice (Sec. 2.3), eo layout of precision p,
+ * full fields.  out and in must not overlap. */
+qxd_status qxd_dw_apply(qxd_handle *h, qxd_prec p, void *out, const void *in, void *stream);
+
+/* out_e = D_hat in_e (dagger = 0) or D_hat^+ in_e = gamma5 D_hat gamma5 in_e
+ * (dagger = 1) (Sec. 2.3), even half fields of precision p.  Uses an internal
+ * odd half field as workspace.  out_e and in_e must not overlap. */
+qxd_status qxd_dw_eo_schur(qxd_handle *h, qxd_prec p, int dagger, void *out_e, const void *in_e, void *stream);
+
+/* bhat_e = b_e - D_eo D_oo^-1 b_o  (F64; b full field, bhat_e even half field). */
+qxd_status qxd_eo_source(qxd_handle *h, void *bhat_e, const void *b, void *stream);
+
+/* x = (x_e, D_oo^-1 (b_o - D_oe x_e))  (F64; x, b full fields, x_e even half). */
+qxd_status qxd_eo_reconstruct(qxd_handle *h, void *x, const void *x_e, const void *b, void *stream);
+
+/* Convert between the canonical AoS layout and the eo layout of precision p.
+ * aos: device pointer to [V][4][3] complex128 (full lattice); soa: full field.
+ * FP64 -> FP32 -> BF16 rounding is to nearest even. */
+qxd_status qxd_pack(qxd_handle *h, qxd_prec p, void *soa, const double *aos, void *stream);
+qxd_status qxd_unpack(qxd_handle *h, qxd_prec p, double *aos, const void *soa, void *stream);
+
+/* Solve D x = b to |b - D x| / |b| <= params->res by CG on the normal equations
+ * of the Schur system, all in FP64 (Sec. 4.4): source preparation, CG, and
+ * reconstruction; the residual is recomputed in FP64 on the full lattice before
+ * returning.  b, x: F64 full fields (device).  stats may be NULL. */
+qxd_status qxd_solve_cg(qxd_handle *h, const qxd_solver_params *params, void *x, const void *b,
+                        qxd_solver_stats *stats, void *stream);
+
+/* Solve D x = b with flexible GCR on D_hat (restart nkv).  With inner_prec F64 a
+ * plain FP64 FGCR; with F32 or BF16 an FP64 defect-correction loop around an
+ * inner FGCR whose operator and vectors are FP32 (BF16: links and spinors stored
+ * in bfloat16).  net: NULL or a network preconditioner M(r) = |r| N(r/|r|) used
+ * inside the inner FGCR, dropped (stats->fell_back = 1) if its directions are
+ * non-finite or the residual stalls for fallback_after steps. */
+qxd_status qxd_solve_fgcr(qxd_handle *h, const qxd_solver_params *params, qxd_nn *net, void *x, const void *b,
+                          qxd_solver_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner: three 3^4-tap convolutions on the extended lattice
+ * whose taps follow the C* neighbour map (x + d is a composition of unit steps),
+ * real channels 24 -> 32 -> 32 -> 24, no biases, ReLU after layers 1 and 2.
+ * Input: an even half spinor embedded on the full lattice with zero odd sites
+ * (channel 2c = Re, 2c+1 = Im of component c); output kept on the even sites.
+ * Weights: FP32 master copy, layers packed one after another, each
+ * [81 taps][cout][cin] with tap = 27(d0+1) + 9(d1+1) + 3(d2+1) + (d3+1);
+ * 207,360 floats in total.  Activations are stored in bfloat16; the
+ * contractions run on MFMA with bfloat16 operands and FP32 accumulation. */
+
+#define QXD_NN_NWEIGHTS 207360
+
+typedef struct {
+  int epochs;
+  int batch;
+  double lr;           /* Adam step size */
+  double beta1, beta2, eps;
+  int holdout;         /* the last `holdout` pairs are not trained on */
+  uint64_t seed;       /* shuffling order */
+} qxd_train_params;
+
+typedef struct {
+  double loss_first;   /* mean training loss of the first epoch */
+  double loss_last;    /* mean training loss of the last epoch */
+  double holdout_loss; /* mean loss on the held-out pairs after training */
+  double t_ms;
+  int64_t steps;
+} qxd_train_stats;
+
+qxd_status qxd_nn_create(qxd_handle *h, qxd_nn **net);
+qxd_status qxd_nn_destroy(qxd_nn *net);
+/* Host pointers to QXD_NN_NWEIGHTS floats (synchronous). */
+qxd_status qxd_nn_set_weights(qxd_nn *net, const float *w);
+qxd_status qxd_nn_get_weights(qxd_nn *net, float *w);
+
+/* out_e = |in_e| N(in_e / |in_e|): F32 even half fields. */
+qxd_status qxd_nn_apply(qxd_handle *h, qxd_nn *net, void *out_e, const void *in_e, void *stream);
+
+/* Loss and FP32 weight gradient (host, QXD_NN_NWEIGHTS floats) over a batch of
+ * pairs: mean_i |N(r_i/|r_i|) - e_i/|r_i||^2 / |e_i/|r_i||^2.  r, e: device arrays
+ * of n F32 even half fields, one after another.  Synchronous. */
+qxd_status qxd_nn_loss_grad(qxd_handle *h, qxd_nn *net, const void *r, const void *e, int n,
+                            double *loss, float *grad, void *stream);
+
+/* Harvest training pairs from an FP64 GCR solve of D_hat x = bhat (no
+ * preconditioner): the residuals r_k and errors e_k = x* - x_k at npairs steps
+ * spread over the solve, stored as F32 even half fields in r_out, e_out (device,
+ * npairs fields each).  b: F64 full field. */
+qxd_status qxd_nn_harvest(qxd_handle *h, const void *b, int npairs, void *r_out, void *e_out,
+                          int *n_harvested, void *stream);
+
+/* Adam training on pairs (r, e) as above; synchronous. */
+qxd_status qxd_nn_train(qxd_handle *h, qxd_nn *net, const qxd_train_params *p, const void *r, const void *e,
+                        int npairs, qxd_train_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QXD_H */

@@ -1,0 +1,91 @@
+// Handle management of libqxd.
+#include <cstdlib>
+#include <new>
+
+#include "qxd_internal.hpp"
+
+extern "C" const char* qxd_status_string(qxd_status s) {
+  switch (s) {
+    case QXD_OK: return "QXD_OK";
+    case QXD_EINVAL: return "QXD_EINVAL";
+    case QXD_EGEOM: return "QXD_EGEOM";
+    case QXD_ENOMEM: return "QXD_ENOMEM";
+    case QXD_ESINGULAR: return "QXD_ESINGULAR";
+    case QXD_ENAN: return "QXD_ENAN";
+    case QXD_ENOCONV: return "QXD_ENOCONV";
+    case QXD_EHIP: return "QXD_EHIP";
+    case QXD_ESTATE: return "QXD_ESTATE";
+  }
+  return "QXD_UNKNOWN";
+}
+
+static void release(qxd_handle* h) {
+  void* ptrs[] = {h->Uphys, h->Aphys, h->V64, h->V32, h->V16, h->He64, h->Ho64, h->Hi64, h->He32,
+                  h->Ho32, h->Hi32, h->t64, h->t32, h->t16, h->partial, h->scal};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int i = 0; i < 64; ++i)
+    if (h->ws[i]) (void)hipFree(h->ws[i]);
+  if (h->scal_host) (void)hipHostFree(h->scal_host);
+}
+
+extern "C" qxd_status qxd_create(const qxd_geom* g, qxd_handle** out) {
+  if (!g || !out) return QXD_EINVAL;
+  *out = nullptr;
+  for (int m = 0; m < 4; ++m)
+    if (g->L[m] < 2 || (g->L[m] & 1)) return QXD_EGEOM;
+  if (g->cstar < 0 || g->cstar > 3) return QXD_EGEOM;
+  int64_t Le1 = g->cstar >= 1 ? 2 * (int64_t)g->L[1] : g->L[1];
+  int64_t V = (int64_t)g->L[0] * Le1 * g->L[2] * g->L[3];
+  if (V >= ((int64_t)1 << 31)) return QXD_EGEOM;
+  qxd_handle* h = new (std::nothrow) qxd_handle();
+  if (!h) return QXD_ENOMEM;
+  h->g = *g;
+  h->V = V;
+  h->Ve = V / 2;
+  h->Vphys = (int64_t)g->L[0] * g->L[1] * g->L[2] * g->L[3];
+  h->geo.Le0 = g->L[0];
+  h->geo.Le1 = (int)Le1;
+  h->geo.Le2 = g->L[2];
+  h->geo.Le3 = g->L[3];
+  h->geo.L1 = g->L[1];
+  h->geo.cstar = g->cstar;
+  h->geo.tanti = g->t_antiperiodic ? 1 : 0;
+  h->geo.L3h = g->L[3] / 2;
+  h->geo.Ve = (int)h->Ve;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return QXD_EHIP;
+  }
+  h->npartial = (size_t)QXD_MAX_PARTIAL;
+  if ((size_t)div_up(h->Ve, QXD_BLOCK) > h->npartial) h->npartial = (size_t)div_up(h->Ve, QXD_BLOCK);
+  if (hipMalloc(&h->partial, h->npartial * sizeof(double)) != hipSuccess ||
+      hipMalloc(&h->scal, QXD_NSCAL * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&h->scal_host, QXD_NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    release(h);
+    delete h;
+    return QXD_ENOMEM;
+  }
+  if (hipMemset(h->scal, 0, QXD_NSCAL * sizeof(double)) != hipSuccess) {
+    release(h);
+    delete h;
+    return QXD_EHIP;
+  }
+  *out = h;
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_destroy(qxd_handle* h) {
+  if (!h) return QXD_EINVAL;
+  (void)hipDeviceSynchronize();
+  release(h);
+  delete h;
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_volume(const qxd_handle* h, int64_t* V, int64_t* Ve) {
+  if (!h) return QXD_EINVAL;
+  if (V) *V = h->V;
+  if (Ve) *Ve = h->Ve;
+  return QXD_OK;
+}

@@ -1,0 +1,336 @@
+// BLAS-1 kernels and deterministic reductions for the Krylov solvers.
+//
+// Vectors are half fields viewed as flat arrays of 16-byte words: double2 (one
+// complex128) or float4 (two complex64).  Reductions are two-pass: each of a
+// fixed number of workgroups reduces its grid-stride share (wave64 shuffles,
+// then LDS) into one partial, and a single-workgroup kernel sums the partials in
+// a fixed order, so results are bitwise reproducible run to run.  Scalars such as
+// CG's alpha and beta are read by the update kernels straight from device
+// memory; the host never waits inside an iteration.
+#include "blas.hpp"
+
+__device__ inline double red_block(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+  return s;
+}
+
+// ---- word helpers ---------------------------------------------------------
+
+__device__ inline double wnorm2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ inline double wnorm2(float4 a) { return (double)(a.x * a.x + a.y * a.y) + (double)(a.z * a.z + a.w * a.w); }
+// conj(a) b
+__device__ inline void wcdot(double2 a, double2 b, double& re, double& im) {
+  re += a.x * b.x + a.y * b.y;
+  im += a.x * b.y - a.y * b.x;
+}
+__device__ inline void wcdot(float4 a, float4 b, double& re, double& im) {
+  re += (double)(a.x * b.x + a.y * b.y) + (double)(a.z * b.z + a.w * b.w);
+  im += (double)(a.x * b.y - a.y * b.x) + (double)(a.z * b.w - a.w * b.z);
+}
+// y + (cr + i ci) x
+__device__ inline double2 wcaxpy(double2 y, double cr, double ci, double2 x) {
+  return make_double2(y.x + cr * x.x - ci * x.y, y.y + cr * x.y + ci * x.x);
+}
+__device__ inline float4 wcaxpy(float4 y, double crd, double cid, float4 x) {
+  float cr = (float)crd, ci = (float)cid;
+  return make_float4(y.x + cr * x.x - ci * x.y, y.y + cr * x.y + ci * x.x, y.z + cr * x.z - ci * x.w,
+                     y.w + cr * x.w + ci * x.z);
+}
+__device__ inline double2 wscale(double2 x, double s) { return make_double2(s * x.x, s * x.y); }
+__device__ inline float4 wscale(float4 x, double sd) {
+  float s = (float)sd;
+  return make_float4(s * x.x, s * x.y, s * x.z, s * x.w);
+}
+__device__ inline double2 wadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline float4 wadd(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+__device__ inline double2 wsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline float4 wsub(float4 a, float4 b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
+__device__ inline bool wfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+#define GRID_STRIDE(i, n) for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+
+// ---- kernels ---------------------------------------------------------------
+
+__global__ __launch_bounds__(QXD_BLOCK) void k_final_sum(const double* __restrict__ partial, int n, int nvals,
+                                                         int stride, double* __restrict__ out) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  for (int v = 0; v < nvals; ++v) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += QXD_BLOCK) a += partial[(size_t)v * stride + i];
+    double s = red_block(a, sh);
+    if (threadIdx.x == 0) out[v] = s;
+  }
+}
+
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_norm2(const VT* __restrict__ x, size_t n, double* __restrict__ partial) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  double a = 0.0;
+  GRID_STRIDE(i, n) a += wnorm2(x[i]);
+  double s = red_block(a, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_cdot(const VT* __restrict__ x, const VT* __restrict__ y, size_t n,
+                                                    double* __restrict__ partial) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  double re = 0.0, im = 0.0;
+  GRID_STRIDE(i, n) wcdot(x[i], y[i], re, im);
+  double s = red_block(re, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  s = red_block(im, sh);
+  if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = s;
+}
+
+// CG: alpha = zz / ww; x += alpha p; r -= alpha w; partial |r|^2
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_cg_xr(VT* __restrict__ x, VT* __restrict__ r, const VT* __restrict__ p,
+                                                     const VT* __restrict__ w, size_t n, const double* __restrict__ scal,
+                                                     int i_zz, int i_ww, double* __restrict__ partial) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  double alpha = scal[i_zz] / scal[i_ww];
+  double a = 0.0;
+  GRID_STRIDE(i, n) {
+    x[i] = wcaxpy(x[i], alpha, 0.0, p[i]);
+    VT rr = wcaxpy(r[i], -alpha, 0.0, w[i]);
+    r[i] = rr;
+    a += wnorm2(rr);
+  }
+  double s = red_block(a, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// CG: beta = zz_new / zz_old; p = z + beta p
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_cg_p(VT* __restrict__ p, const VT* __restrict__ z, size_t n,
+                                                    const double* __restrict__ scal, int i_new, int i_old) {
+  double beta = scal[i_new] / scal[i_old];
+  GRID_STRIDE(i, n) p[i] = wcaxpy(z[i], beta, 0.0, p[i]);
+}
+
+// r = b - w; partial |r|^2
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_sub_norm(VT* __restrict__ r, const VT* __restrict__ b,
+                                                        const VT* __restrict__ w, size_t n,
+                                                        double* __restrict__ partial) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  double a = 0.0;
+  GRID_STRIDE(i, n) {
+    VT v = wsub(b[i], w[i]);
+    r[i] = v;
+    a += wnorm2(v);
+  }
+  double s = red_block(a, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// dots (basis_j, v) for j < k: partial[(2j) G + b] = Re, [(2j+1) G + b] = Im
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_mdot(Ptrs basis, int k, const VT* __restrict__ v, size_t n,
+                                                    double* __restrict__ partial) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  double re[QXD_MAXKV], im[QXD_MAXKV];
+#pragma unroll
+  for (int j = 0; j < QXD_MAXKV; ++j) re[j] = im[j] = 0.0;
+  GRID_STRIDE(i, n) {
+    VT vi = v[i];
+#pragma unroll
+    for (int j = 0; j < QXD_MAXKV; ++j)
+      if (j < k) wcdot(((const VT*)basis.p[j])[i], vi, re[j], im[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < QXD_MAXKV; ++j) {
+    if (j < k) {
+      double s = red_block(re[j], sh);
+      if (threadIdx.x == 0) partial[(size_t)(2 * j) * gridDim.x + blockIdx.x] = s;
+      s = red_block(im[j], sh);
+      if (threadIdx.x == 0) partial[(size_t)(2 * j + 1) * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// v -= sum_j c_j basis_j (c complex at coef[2j], coef[2j+1]); partial |v|^2
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_mupdate(VT* __restrict__ v, Ptrs basis, int k,
+                                                       const double* __restrict__ coef, size_t n,
+                                                       double* __restrict__ partial) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  double a = 0.0;
+  GRID_STRIDE(i, n) {
+    VT vi = v[i];
+    for (int j = 0; j < k; ++j) vi = wcaxpy(vi, -coef[2 * j], -coef[2 * j + 1], ((const VT*)basis.p[j])[i]);
+    v[i] = vi;
+    a += wnorm2(vi);
+  }
+  double s = red_block(a, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// v *= 1/sqrt(scal[i_n2]); partial (v, r)
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_scale_cdot(VT* __restrict__ v, const VT* __restrict__ r, size_t n,
+                                                          const double* __restrict__ scal, int i_n2,
+                                                          double* __restrict__ partial) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  double sc = 1.0 / sqrt(scal[i_n2]);
+  double re = 0.0, im = 0.0;
+  GRID_STRIDE(i, n) {
+    VT vi = wscale(v[i], sc);
+    v[i] = vi;
+    wcdot(vi, r[i], re, im);
+  }
+  double s = red_block(re, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  s = red_block(im, sh);
+  if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = s;
+}
+
+// r -= c v (c complex at scal[i_c]); partial |r|^2
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_r_update(VT* __restrict__ r, const VT* __restrict__ v, size_t n,
+                                                        const double* __restrict__ scal, int i_c,
+                                                        double* __restrict__ partial) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  double cr = scal[i_c], ci = scal[i_c + 1];
+  double a = 0.0;
+  GRID_STRIDE(i, n) {
+    VT ri = wcaxpy(r[i], -cr, -ci, v[i]);
+    r[i] = ri;
+    a += wnorm2(ri);
+  }
+  double s = red_block(a, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// x += sum_j c_j basis_j
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_multi_axpy(VT* __restrict__ x, Ptrs basis, int k,
+                                                          const double* __restrict__ coef, size_t n) {
+  GRID_STRIDE(i, n) {
+    VT xi = x[i];
+    for (int j = 0; j < k; ++j) xi = wcaxpy(xi, coef[2 * j], coef[2 * j + 1], ((const VT*)basis.p[j])[i]);
+    x[i] = xi;
+  }
+}
+
+template <class VT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_zero(VT* __restrict__ x, size_t n) {
+  GRID_STRIDE(i, n) x[i] = VT{};
+}
+
+// d (FP32, n2 words = 2 complex each) = s / sqrt(scal[i])  (s FP64)
+__global__ __launch_bounds__(QXD_BLOCK) void k_down(float4* __restrict__ d, const double2* __restrict__ s, size_t nw,
+                                                    const double* __restrict__ scal, int i_n2) {
+  double sc = 1.0 / sqrt(scal[i_n2]);
+  GRID_STRIDE(i, nw) {
+    double2 a = s[2 * i], b = s[2 * i + 1];
+    d[i] = make_float4((float)(sc * a.x), (float)(sc * a.y), (float)(sc * b.x), (float)(sc * b.y));
+  }
+}
+
+// x (FP64) += sqrt(scal[i]) e (FP32)
+__global__ __launch_bounds__(QXD_BLOCK) void k_up_acc(double2* __restrict__ x, const float4* __restrict__ e, size_t nw,
+                                                      const double* __restrict__ scal, int i_n2) {
+  double sc = sqrt(scal[i_n2]);
+  GRID_STRIDE(i, nw) {
+    float4 v = e[i];
+    double2 a = x[2 * i], b = x[2 * i + 1];
+    x[2 * i] = make_double2(a.x + sc * (double)v.x, a.y + sc * (double)v.y);
+    x[2 * i + 1] = make_double2(b.x + sc * (double)v.z, b.y + sc * (double)v.w);
+  }
+}
+
+// ---- host launchers -------------------------------------------------------
+
+void launch_final_sum(const double* partial, int n, int nvals, int stride, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(QXD_BLOCK), 0, s, partial, n, nvals, stride, out);
+}
+
+template <class VT>
+void blas_norm2(qxd_handle* h, const VT* x, size_t n, double* slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm2<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, n, h->partial);
+  launch_final_sum(h->partial, QXD_NRED, 1, QXD_NRED, slot, s);
+}
+template <class VT>
+void blas_cdot(qxd_handle* h, const VT* x, const VT* y, size_t n, double* slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_cdot<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, y, n, h->partial);
+  launch_final_sum(h->partial, QXD_NRED, 2, QXD_NRED, slot, s);
+}
+template <class VT>
+void blas_cg_xr(qxd_handle* h, VT* x, VT* r, const VT* p, const VT* w, size_t n, int i_zz, int i_ww, int i_rr,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_xr<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, r, p, w, n, h->scal, i_zz, i_ww,
+                     h->partial);
+  launch_final_sum(h->partial, QXD_NRED, 1, QXD_NRED, h->scal + i_rr, s);
+}
+template <class VT>
+void blas_cg_p(qxd_handle* h, VT* p, const VT* z, size_t n, int i_new, int i_old, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, p, z, n, h->scal, i_new, i_old);
+}
+template <class VT>
+void blas_sub_norm(qxd_handle* h, VT* r, const VT* b, const VT* w, size_t n, double* slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_norm<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, r, b, w, n, h->partial);
+  launch_final_sum(h->partial, QXD_NRED, 1, QXD_NRED, slot, s);
+}
+template <class VT>
+void blas_mdot(qxd_handle* h, const Ptrs& basis, int k, const VT* v, size_t n, double* slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, basis, k, v, n, h->partial);
+  launch_final_sum(h->partial, QXD_NRED, 2 * k, QXD_NRED, slots, s);
+}
+template <class VT>
+void blas_mupdate(qxd_handle* h, VT* v, const Ptrs& basis, int k, const double* coef, size_t n, double* slot,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_mupdate<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, v, basis, k, coef, n, h->partial);
+  launch_final_sum(h->partial, QXD_NRED, 1, QXD_NRED, slot, s);
+}
+template <class VT>
+void blas_scale_cdot(qxd_handle* h, VT* v, const VT* r, size_t n, int i_n2, double* slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_cdot<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, v, r, n, h->scal, i_n2, h->partial);
+  launch_final_sum(h->partial, QXD_NRED, 2, QXD_NRED, slots, s);
+}
+template <class VT>
+void blas_r_update(qxd_handle* h, VT* r, const VT* v, size_t n, int i_c, double* slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_r_update<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, r, v, n, h->scal, i_c, h->partial);
+  launch_final_sum(h->partial, QXD_NRED, 1, QXD_NRED, slot, s);
+}
+template <class VT>
+void blas_multi_axpy(qxd_handle* h, VT* x, const Ptrs& basis, int k, const double* coef, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_multi_axpy<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, basis, k, coef, n);
+}
+template <class VT>
+void blas_zero(VT* x, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, n);
+}
+void blas_down(qxd_handle* h, float4* d, const double2* src, size_t nw, int i_n2, hipStream_t s) {
+  hipLaunchKernelGGL(k_down, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, d, src, nw, h->scal, i_n2);
+}
+void blas_up_acc(qxd_handle* h, double2* x, const float4* e, size_t nw, int i_n2, hipStream_t s) {
+  hipLaunchKernelGGL(k_up_acc, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, e, nw, h->scal, i_n2);
+}
+
+#define INST(VT)                                                                                        \
+  template void blas_norm2<VT>(qxd_handle*, const VT*, size_t, double*, hipStream_t);                  \
+  template void blas_cdot<VT>(qxd_handle*, const VT*, const VT*, size_t, double*, hipStream_t);        \
+  template void blas_cg_xr<VT>(qxd_handle*, VT*, VT*, const VT*, const VT*, size_t, int, int, int,      \
+                               hipStream_t);                                                            \
+  template void blas_cg_p<VT>(qxd_handle*, VT*, const VT*, size_t, int, int, hipStream_t);              \
+  template void blas_sub_norm<VT>(qxd_handle*, VT*, const VT*, const VT*, size_t, double*, hipStream_t); \
+  template void blas_mdot<VT>(qxd_handle*, const Ptrs&, int, const VT*, size_t, double*, hipStream_t);  \
+  template void blas_mupdate<VT>(qxd_handle*, VT*, const Ptrs&, int, const double*, size_t, double*,    \
+                                 hipStream_t);                                                          \
+  template void blas_scale_cdot<VT>(qxd_handle*, VT*, const VT*, size_t, int, double*, hipStream_t);    \
+  template void blas_r_update<VT>(qxd_handle*, VT*, const VT*, size_t, int, double*, hipStream_t);      \
+  template void blas_multi_axpy<VT>(qxd_handle*, VT*, const Ptrs&, int, const double*, size_t,          \
+                                    hipStream_t);                                                       \
+  template void blas_zero<VT>(VT*, size_t, hipStream_t);
+
+INST(double2)
+INST(float4)

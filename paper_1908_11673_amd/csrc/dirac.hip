@@ -1,0 +1,450 @@
+// Wilson-clover operator with SU(3) x U(1)^qhat links on the C* extended lattice
+// and its even-odd Schur complement (Sec. 2.3 of arXiv:1908.11673).
+//
+// Expanding the covariant derivatives of Dw gives, with V = U z^qhat,
+//   (D psi)(x) = H(x) psi(x) - (1/2) hop(psi)(x),
+//   hop(psi)(x) = sum_mu (1 - g_mu) V(x,mu) psi(x+mu) + (1 + g_mu) V(x-mu,mu)^+ psi(x-mu),
+// H = 1/(2 kappa) + SW term (two 6x6 chirality blocks).  Each (1 -+ g_mu) term is
+// evaluated on a projected two-spinor: project, multiply by the link, rebuild.
+// Hops always connect the two parities, so
+//   D_hat psi_e = H_e psi_e - (1/4) hop_eo( H_o^-1 hop_oe(psi_e) ),
+// computed in two passes (odd sites, then even sites); D_hat^+ = g5 D_hat g5.
+// One work-item per output site; neighbours are found from the site
+// coordinates (no neighbour table), including the C* shift of x1 when a hop in
+// direction k <= cstar crosses the lattice boundary.
+#include "qxd_internal.hpp"
+
+// Add (1 - g_MU) W s (FWD) or (1 + g_MU) W^+ s (backward) to acc, W the link u.
+template <int MU, bool FWD, class T>
+__device__ __forceinline__ void hop_term(cx<T> acc[12], const cx<T> s[12], const cx<T> u[9], bool neg) {
+  cx<T> h0[3], h1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cx<T> s0 = s[a], s1 = s[3 + a], s2 = s[6 + a], s3 = s[9 + a];
+    if (MU == 0) {
+      h0[a] = FWD ? s0 + s2 : s0 - s2;
+      h1[a] = FWD ? s1 + s3 : s1 - s3;
+    } else if (MU == 1) {
+      h0[a] = FWD ? s0 + ti(s3) : s0 - ti(s3);
+      h1[a] = FWD ? s1 + ti(s2) : s1 - ti(s2);
+    } else if (MU == 2) {
+      h0[a] = FWD ? s0 + s3 : s0 - s3;
+      h1[a] = FWD ? s1 - s2 : s1 + s2;
+    } else {
+      h0[a] = FWD ? s0 + ti(s2) : s0 - ti(s2);
+      h1[a] = FWD ? s1 - ti(s3) : s1 + ti(s3);
+    }
+  }
+  if (MU == 0 && neg) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      h0[a] = -h0[a];
+      h1[a] = -h1[a];
+    }
+  }
+  cx<T> w0[3], w1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (FWD) {
+      w0[a] = u[3 * a] * h0[0] + u[3 * a + 1] * h0[1] + u[3 * a + 2] * h0[2];
+      w1[a] = u[3 * a] * h1[0] + u[3 * a + 1] * h1[1] + u[3 * a + 2] * h1[2];
+    } else {
+      w0[a] = cmul_conj(u[a], h0[0]) + cmul_conj(u[3 + a], h0[1]) + cmul_conj(u[6 + a], h0[2]);
+      w1[a] = cmul_conj(u[a], h1[0]) + cmul_conj(u[3 + a], h1[1]) + cmul_conj(u[6 + a], h1[2]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[a] = acc[a] + w0[a];
+    acc[3 + a] = acc[3 + a] + w1[a];
+    if (MU == 0) {
+      acc[6 + a] = FWD ? acc[6 + a] + w0[a] : acc[6 + a] - w0[a];
+      acc[9 + a] = FWD ? acc[9 + a] + w1[a] : acc[9 + a] - w1[a];
+    } else if (MU == 1) {
+      acc[6 + a] = FWD ? acc[6 + a] - ti(w1[a]) : acc[6 + a] + ti(w1[a]);
+      acc[9 + a] = FWD ? acc[9 + a] - ti(w0[a]) : acc[9 + a] + ti(w0[a]);
+    } else if (MU == 2) {
+      acc[6 + a] = FWD ? acc[6 + a] - w1[a] : acc[6 + a] + w1[a];
+      acc[9 + a] = FWD ? acc[9 + a] + w0[a] : acc[9 + a] - w0[a];
+    } else {
+      acc[6 + a] = FWD ? acc[6 + a] - ti(w0[a]) : acc[6 + a] + ti(w0[a]);
+      acc[9 + a] = FWD ? acc[9 + a] + ti(w1[a]) : acc[9 + a] - ti(w1[a]);
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void g5_lower(cx<T> s[12]) {
+#pragma unroll
+  for (int c = 6; c < 12; ++c) s[c] = -s[c];
+}
+
+// Both hops along MU for the site (p, h) at coordinates x: links of own parity
+// are Vp, of the other parity Vq; the field `in` lives on the other parity.
+template <int MU, bool G5IN, class T, class SPT, class LKT>
+__device__ __forceinline__ void hop_mu(const Geo& g, int h, int x0, int x1, int x2, int x3,
+                                       const SPT* __restrict__ in, const LKT* __restrict__ Vp,
+                                       const LKT* __restrict__ Vq, cx<T> acc[12]) {
+  const size_t Ve = g.Ve;
+  bool negf, negb;
+  int hf = geo_nb<MU, +1>(g, x0, x1, x2, x3, negf);
+  int hb = geo_nb<MU, -1>(g, x0, x1, x2, x3, negb);
+  cx<T> s[12], u[9];
+  sp_load(in, Ve, hf, s);
+  if (G5IN) g5_lower(s);
+  lk_load(Vp, Ve, MU, h, u);
+  hop_term<MU, true>(acc, s, u, negf);
+  sp_load(in, Ve, hb, s);
+  if (G5IN) g5_lower(s);
+  lk_load(Vq, Ve, MU, hb, u);
+  hop_term<MU, false>(acc, s, u, negb);
+}
+
+template <bool G5IN, class T, class SPT, class LKT>
+__device__ __forceinline__ void hop_site(const Geo& g, int p, int h, const SPT* __restrict__ in,
+                                         const LKT* __restrict__ Vp, const LKT* __restrict__ Vq, cx<T> acc[12]) {
+  int x0, x1, x2, x3;
+  geo_decode(g, p, h, x0, x1, x2, x3);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = mk(T(0), T(0));
+  hop_mu<0, G5IN, T>(g, h, x0, x1, x2, x3, in, Vp, Vq, acc);
+  hop_mu<1, G5IN, T>(g, h, x0, x1, x2, x3, in, Vp, Vq, acc);
+  hop_mu<2, G5IN, T>(g, h, x0, x1, x2, x3, in, Vp, Vq, acc);
+  hop_mu<3, G5IN, T>(g, h, x0, x1, x2, x3, in, Vp, Vq, acc);
+}
+
+template <class T, class CLT>
+__device__ __forceinline__ void clover_mul(const CLT* __restrict__ C, size_t Ve, int h, const cx<T> in[12],
+                                           cx<T> out[12]) {
+  T r[72];
+  cl_load(C, Ve, h, r);
+  herm6_mul<T>(r, in, out);
+  herm6_mul<T>(r + 36, in + 6, out + 6);
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+  return s;
+}
+
+template <class T>
+__device__ __forceinline__ double sp_norm2(const cx<T> s[12]) {
+  double a = 0.0;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) a += (double)norm2(s[c]);
+  return a;
+}
+
+// pass 1: t_o = H_o^-1 hop_oe(g5? psi_e)
+template <class T, class SPT, class LKT, class CLT, bool DAG>
+__global__ __launch_bounds__(QXD_BLOCK) void k_schur1(Geo g, const SPT* __restrict__ in_e, SPT* __restrict__ t_o,
+                                                      const LKT* __restrict__ Ve_l, const LKT* __restrict__ Vo_l,
+                                                      const CLT* __restrict__ Hi) {
+  int h = xcd_tile(blockIdx.x, gridDim.x) * QXD_BLOCK + threadIdx.x;
+  if (h >= g.Ve) return;
+  cx<T> acc[12], out[12];
+  hop_site<DAG, T>(g, 1, h, in_e, Vo_l, Ve_l, acc);
+  clover_mul<T>(Hi, g.Ve, h, acc, out);
+  sp_store(t_o, g.Ve, h, out);
+}
+
+// pass 2: out_e = H_e psi_e - (1/4) g5? hop_eo(t_o); optional block partials of |out|^2
+template <class T, class SPT, class LKT, class CLT, bool DAG, bool NORM>
+__global__ __launch_bounds__(QXD_BLOCK) void k_schur2(Geo g, const SPT* __restrict__ t_o,
+                                                      const SPT* __restrict__ in_e, SPT* __restrict__ out_e,
+                                                      const LKT* __restrict__ Ve_l, const LKT* __restrict__ Vo_l,
+                                                      const CLT* __restrict__ He, double* __restrict__ partial) {
+  __shared__ double sh[QXD_BLOCK / 64];
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  int h = tile * QXD_BLOCK + threadIdx.x;
+  double n2 = 0.0;
+  if (h < g.Ve) {
+    cx<T> acc[12], s[12], c[12];
+    hop_site<false, T>(g, 0, h, t_o, Ve_l, Vo_l, acc);
+    if (DAG) g5_lower(acc);
+    sp_load(in_e, g.Ve, h, s);
+    clover_mul<T>(He, g.Ve, h, s, c);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c[k] = c[k] - T(0.25) * acc[k];
+    sp_store(out_e, g.Ve, h, c);
+    if (NORM) n2 = sp_norm2(c);
+  }
+  if (NORM) {
+    double b = block_sum(n2, sh);
+    if (threadIdx.x == 0) partial[tile] = b;
+  }
+}
+
+// full operator on parity p: out_p = H_p in_p - (1/2) hop(in_q)
+template <class T, class SPT, class LKT, class CLT>
+__global__ __launch_bounds__(QXD_BLOCK) void k_dw(Geo g, int p, const SPT* __restrict__ in_p,
+                                                  const SPT* __restrict__ in_q, SPT* __restrict__ out_p,
+                                                  const LKT* __restrict__ Vp, const LKT* __restrict__ Vq,
+                                                  const CLT* __restrict__ Hp) {
+  int h = xcd_tile(blockIdx.x, gridDim.x) * QXD_BLOCK + threadIdx.x;
+  if (h >= g.Ve) return;
+  cx<T> acc[12], s[12], c[12];
+  hop_site<false, T>(g, p, h, in_q, Vp, Vq, acc);
+  sp_load(in_p, g.Ve, h, s);
+  clover_mul<T>(Hp, g.Ve, h, s, c);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) c[k] = c[k] - T(0.5) * acc[k];
+  sp_store(out_p, g.Ve, h, c);
+}
+
+// out_p = C? (base_p + alpha hop(in_q))   (FP64; source preparation and reconstruction)
+template <bool CLOV>
+__global__ __launch_bounds__(QXD_BLOCK) void k_hop_add(Geo g, int p, const double2* __restrict__ in_q,
+                                                       const double2* __restrict__ base, double2* __restrict__ out,
+                                                       const double2* __restrict__ Vp, const double2* __restrict__ Vq,
+                                                       const double2* __restrict__ C, double alpha) {
+  int h = xcd_tile(blockIdx.x, gridDim.x) * QXD_BLOCK + threadIdx.x;
+  if (h >= g.Ve) return;
+  cx<double> acc[12], s[12], c[12];
+  hop_site<false, double>(g, p, h, in_q, Vp, Vq, acc);
+  sp_load(base, g.Ve, h, s);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) s[k] = s[k] + alpha * acc[k];
+  if (CLOV) {
+    clover_mul<double>(C, g.Ve, h, s, c);
+    sp_store(out, g.Ve, h, c);
+  } else {
+    sp_store(out, g.Ve, h, s);
+  }
+}
+
+// out = C in on one parity
+__global__ __launch_bounds__(QXD_BLOCK) void k_clov(int Ve, const double2* __restrict__ in, double2* __restrict__ out,
+                                                    const double2* __restrict__ C) {
+  int h = blockIdx.x * QXD_BLOCK + threadIdx.x;
+  if (h >= Ve) return;
+  cx<double> s[12], c[12];
+  sp_load(in, Ve, h, s);
+  clover_mul<double>(C, Ve, h, s, c);
+  sp_store(out, Ve, h, c);
+}
+
+// canonical AoS [V][12] complex128 <-> eo SoA of the storage type
+template <class SPT, class T>
+__global__ __launch_bounds__(QXD_BLOCK) void k_unpack(Geo g, double2* __restrict__ aos, const SPT* __restrict__ soa,
+                                                      int groups) {
+  int64_t t = (int64_t)blockIdx.x * QXD_BLOCK + threadIdx.x;
+  if (t >= 2 * (int64_t)g.Ve) return;
+  int p = (int)(t / g.Ve), h = (int)(t % g.Ve);
+  int x0, x1, x2, x3;
+  geo_decode(g, p, h, x0, x1, x2, x3);
+  int64_t s = (int64_t)x3 + (int64_t)g.Le3 * ((int64_t)x2 + (int64_t)g.Le2 * ((int64_t)x1 + (int64_t)g.Le1 * x0));
+  cx<T> v[12];
+  sp_load(soa + (size_t)p * groups * g.Ve, g.Ve, h, v);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) aos[s * 12 + c] = make_double2((double)v[c].re, (double)v[c].im);
+}
+
+template <class SPT, class T>
+__global__ __launch_bounds__(QXD_BLOCK) void k_pack2(Geo g, SPT* __restrict__ soa, const double2* __restrict__ aos,
+                                                     int groups) {
+  int64_t t = (int64_t)blockIdx.x * QXD_BLOCK + threadIdx.x;
+  if (t >= 2 * (int64_t)g.Ve) return;
+  int p = (int)(t / g.Ve), h = (int)(t % g.Ve);
+  int x0, x1, x2, x3;
+  geo_decode(g, p, h, x0, x1, x2, x3);
+  int64_t s = (int64_t)x3 + (int64_t)g.Le3 * ((int64_t)x2 + (int64_t)g.Le2 * ((int64_t)x1 + (int64_t)g.Le1 * x0));
+  cx<T> v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    double2 a = aos[s * 12 + c];
+    v[c] = mk((T)a.x, (T)a.y);
+  }
+  sp_store(soa + (size_t)p * groups * g.Ve, g.Ve, h, v);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static int groups_of(qxd_prec p) { return p == QXD_F64 ? 12 : p == QXD_F32 ? 6 : 3; }
+
+static size_t half_bytes(const qxd_handle* h, qxd_prec p) { return (size_t)groups_of(p) * 16 * h->Ve; }
+
+static qxd_status ensure_t(qxd_handle* h, qxd_prec p) {
+  void** t = p == QXD_F64 ? (void**)&h->t64 : p == QXD_F32 ? (void**)&h->t32 : (void**)&h->t16;
+  if (!*t && hipMalloc(t, half_bytes(h, p)) != hipSuccess) return QXD_ENOMEM;
+  return QXD_OK;
+}
+
+
+template <class T, class SPT, class LKT, class CLT>
+static void launch_schur(qxd_handle* h, int dagger, SPT* out, const SPT* in, SPT* t, const LKT* V, const CLT* He,
+                         const CLT* Hi, double* norm_slot, hipStream_t s) {
+  const size_t lk_half = (size_t)4 * 9 * h->Ve;
+  const LKT* Ve_l = V;
+  const LKT* Vo_l = V + lk_half;
+  int G = div_up(h->Ve, QXD_BLOCK);
+  if (dagger)
+    hipLaunchKernelGGL((k_schur1<T, SPT, LKT, CLT, true>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, in, t, Ve_l, Vo_l, Hi);
+  else
+    hipLaunchKernelGGL((k_schur1<T, SPT, LKT, CLT, false>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, in, t, Ve_l, Vo_l, Hi);
+  if (norm_slot) {
+    if (dagger)
+      hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, true, true>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, t, in, out,
+                         Ve_l, Vo_l, He, h->partial);
+    else
+      hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, false, true>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, t, in, out,
+                         Ve_l, Vo_l, He, h->partial);
+    launch_final_sum(h->partial, G, 1, G, norm_slot, s);
+  } else {
+    if (dagger)
+      hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, true, false>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, t, in, out,
+                         Ve_l, Vo_l, He, nullptr);
+    else
+      hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, false, false>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, t, in, out,
+                         Ve_l, Vo_l, He, nullptr);
+  }
+}
+
+qxd_status qxd_schur_apply(qxd_handle* h, qxd_prec p, int dagger, void* out_e, const void* in_e, double* norm_slot,
+                           hipStream_t s) {
+  if (!h->has_inverse) return QXD_ESTATE;
+  QXD_TRY(ensure_t(h, p));
+  switch (p) {
+    case QXD_F64:
+      launch_schur<double>(h, dagger, (double2*)out_e, (const double2*)in_e, h->t64, (const double2*)h->V64,
+                           (const double2*)h->He64, (const double2*)h->Hi64, norm_slot, s);
+      break;
+    case QXD_F32:
+      launch_schur<float>(h, dagger, (float4*)out_e, (const float4*)in_e, h->t32, (const float2*)h->V32,
+                          (const float4*)h->He32, (const float4*)h->Hi32, norm_slot, s);
+      break;
+    case QXD_BF16:
+      launch_schur<float>(h, dagger, (uint4*)out_e, (const uint4*)in_e, h->t16, (const uint32_t*)h->V16,
+                          (const float4*)h->He32, (const float4*)h->Hi32, norm_slot, s);
+      break;
+    default:
+      return QXD_EINVAL;
+  }
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}
+
+// BF16 links with FP32 spinors (the inner operator of the BF16 solver mode)
+qxd_status qxd_schur_apply_mixed(qxd_handle* h, int dagger, float4* out_e, const float4* in_e, double* norm_slot,
+                                 hipStream_t s) {
+  if (!h->has_inverse) return QXD_ESTATE;
+  QXD_TRY(ensure_t(h, QXD_F32));
+  launch_schur<float>(h, dagger, out_e, in_e, h->t32, (const uint32_t*)h->V16, (const float4*)h->He32,
+                      (const float4*)h->Hi32, norm_slot, s);
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_dw_eo_schur(qxd_handle* h, qxd_prec p, int dagger, void* out_e, const void* in_e,
+                                      void* stream) {
+  if (!h || !out_e || !in_e || out_e == in_e) return QXD_EINVAL;
+  if (p != QXD_F64 && p != QXD_F32 && p != QXD_BF16) return QXD_EINVAL;
+  return qxd_schur_apply(h, p, dagger ? 1 : 0, out_e, in_e, nullptr, as_stream(stream));
+}
+
+template <class T, class SPT, class LKT, class CLT>
+static void launch_dw(qxd_handle* h, SPT* out, const SPT* in, const LKT* V, const CLT* He, const CLT* Ho, int groups,
+                      hipStream_t s) {
+  const size_t lk_half = (size_t)4 * 9 * h->Ve;
+  const size_t sp_half = (size_t)groups * h->Ve;
+  int G = div_up(h->Ve, QXD_BLOCK);
+  hipLaunchKernelGGL((k_dw<T, SPT, LKT, CLT>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, 0, in, in + sp_half, out, V,
+                     V + lk_half, He);
+  hipLaunchKernelGGL((k_dw<T, SPT, LKT, CLT>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, 1, in + sp_half, in,
+                     out + sp_half, V + lk_half, V, Ho);
+}
+
+extern "C" qxd_status qxd_dw_apply(qxd_handle* h, qxd_prec p, void* out, const void* in, void* stream) {
+  if (!h || !out || !in || out == in) return QXD_EINVAL;
+  if (!h->has_clover) return QXD_ESTATE;
+  hipStream_t s = as_stream(stream);
+  switch (p) {
+    case QXD_F64:
+      launch_dw<double>(h, (double2*)out, (const double2*)in, (const double2*)h->V64, (const double2*)h->He64,
+                        (const double2*)h->Ho64, 12, s);
+      break;
+    case QXD_F32:
+    case QXD_BF16:
+      if (!h->has_inverse) return QXD_ESTATE;  // FP32 clover copies are made by clover_invert
+      if (p == QXD_F32)
+        launch_dw<float>(h, (float4*)out, (const float4*)in, (const float2*)h->V32, (const float4*)h->He32,
+                         (const float4*)h->Ho32, 6, s);
+      else
+        launch_dw<float>(h, (uint4*)out, (const uint4*)in, (const uint32_t*)h->V16, (const float4*)h->He32,
+                         (const float4*)h->Ho32, 3, s);
+      break;
+    default:
+      return QXD_EINVAL;
+  }
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_eo_source(qxd_handle* h, void* bhat_e, const void* b, void* stream) {
+  if (!h || !bhat_e || !b) return QXD_EINVAL;
+  if (!h->has_inverse) return QXD_ESTATE;
+  QXD_TRY(ensure_t(h, QXD_F64));
+  hipStream_t s = as_stream(stream);
+  const double2* bb = (const double2*)b;
+  const size_t sp_half = (size_t)12 * h->Ve, lk_half = (size_t)4 * 9 * h->Ve;
+  int G = div_up(h->Ve, QXD_BLOCK);
+  // t_o = H_o^-1 b_o ;  bhat_e = b_e + (1/2) hop(t_o)
+  hipLaunchKernelGGL(k_clov, dim3(G), dim3(QXD_BLOCK), 0, s, (int)h->Ve, bb + sp_half, h->t64, (const double2*)h->Hi64);
+  hipLaunchKernelGGL(k_hop_add<false>, dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, 0, h->t64, bb, (double2*)bhat_e,
+                     h->V64, h->V64 + lk_half, nullptr, 0.5);
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_eo_reconstruct(qxd_handle* h, void* x, const void* x_e, const void* b, void* stream) {
+  if (!h || !x || !x_e || !b) return QXD_EINVAL;
+  if (!h->has_inverse) return QXD_ESTATE;
+  hipStream_t s = as_stream(stream);
+  const size_t sp_half = (size_t)12 * h->Ve, lk_half = (size_t)4 * 9 * h->Ve;
+  double2* xx = (double2*)x;
+  if (x_e != x) QXD_HIP(hipMemcpyAsync(xx, x_e, sp_half * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  int G = div_up(h->Ve, QXD_BLOCK);
+  // x_o = H_o^-1 (b_o + (1/2) hop(x_e))
+  hipLaunchKernelGGL(k_hop_add<true>, dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, 1, (const double2*)xx,
+                     (const double2*)b + sp_half, xx + sp_half, h->V64 + lk_half, h->V64, (const double2*)h->Hi64,
+                     0.5);
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_pack(qxd_handle* h, qxd_prec p, void* soa, const double* aos, void* stream) {
+  if (!h || !soa || !aos) return QXD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  int G = div_up(2 * h->Ve, QXD_BLOCK);
+  const double2* a = (const double2*)aos;
+  switch (p) {
+    case QXD_F64: hipLaunchKernelGGL((k_pack2<double2, double>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, (double2*)soa, a, 12); break;
+    case QXD_F32: hipLaunchKernelGGL((k_pack2<float4, float>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, (float4*)soa, a, 6); break;
+    case QXD_BF16: hipLaunchKernelGGL((k_pack2<uint4, float>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, (uint4*)soa, a, 3); break;
+    default: return QXD_EINVAL;
+  }
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_unpack(qxd_handle* h, qxd_prec p, double* aos, const void* soa, void* stream) {
+  if (!h || !soa || !aos) return QXD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  int G = div_up(2 * h->Ve, QXD_BLOCK);
+  double2* a = (double2*)aos;
+  switch (p) {
+    case QXD_F64: hipLaunchKernelGGL((k_unpack<double2, double>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, a, (const double2*)soa, 12); break;
+    case QXD_F32: hipLaunchKernelGGL((k_unpack<float4, float>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, a, (const float4*)soa, 6); break;
+    case QXD_BF16: hipLaunchKernelGGL((k_unpack<uint4, float>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, a, (const uint4*)soa, 3); break;
+    default: return QXD_EINVAL;
+  }
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}

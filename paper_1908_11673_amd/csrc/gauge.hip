@@ -1,0 +1,98 @@
+// Gauge preparation on the extended lattice (Sec. 2.1 and 2.3 of arXiv:1908.11673):
+// the mirror half U(x + L1 e1) = U(x)*, A(x + L1 e1) = -A(x) is filled from the
+// physical half on the fly, and the combined links V(x,mu) = U(x,mu) z(x,mu)^qhat
+// with z = exp(i A) are written in the even-odd SoA layout in FP64, FP32 and BF16.
+#include "qxd_internal.hpp"
+
+// canonical physical site of extended coordinates, and whether x is on the mirror half
+__device__ inline int64_t phys_site(const Geo& g, const int Lp[4], int x0, int x1, int x2, int x3, bool& mirror) {
+  mirror = x1 >= Lp[1];
+  int x1p = mirror ? x1 - Lp[1] : x1;
+  return (int64_t)x3 + (int64_t)Lp[3] * ((int64_t)x2 + (int64_t)Lp[2] * ((int64_t)x1p + (int64_t)Lp[1] * x0));
+}
+
+struct PhysExt {
+  int L[4];
+  int64_t Vphys;
+};
+
+__global__ __launch_bounds__(QXD_BLOCK) void k_make_links(Geo g, PhysExt pe, const double2* __restrict__ U,
+                                                           const double* __restrict__ A, int qhat,
+                                                           double2* __restrict__ V64, float2* __restrict__ V32,
+                                                           uint32_t* __restrict__ V16) {
+  int64_t t = (int64_t)blockIdx.x * QXD_BLOCK + threadIdx.x;
+  int64_t total = 2 * (int64_t)g.Ve * 4;
+  if (t >= total) return;
+  int h = (int)(t % g.Ve);
+  int rest = (int)(t / g.Ve);
+  int mu = rest & 3;
+  int p = rest >> 2;
+  int x0, x1, x2, x3;
+  geo_decode(g, p, h, x0, x1, x2, x3);
+  bool mirror;
+  int64_t sp = phys_site(g, pe.L, x0, x1, x2, x3, mirror);
+  double a = A[mu * pe.Vphys + sp];
+  if (mirror) a = -a;
+  double sn, cs;
+  sincos((double)qhat * a, &sn, &cs);
+  cx<double> z = mk(cs, sn);
+  size_t Ve = g.Ve;
+  size_t base = ((size_t)(p * 4 + mu) * 9) * Ve + h;
+  for (int k = 0; k < 9; ++k) {
+    double2 u = U[(mu * pe.Vphys + sp) * 9 + k];
+    cx<double> uu = mk(u.x, mirror ? -u.y : u.y);
+    cx<double> v = uu * z;
+    V64[base + k * Ve] = make_double2(v.re, v.im);
+    float fr = (float)v.re, fi = (float)v.im;
+    V32[base + k * Ve] = make_float2(fr, fi);
+    V16[base + k * Ve] = pack_bf16x2(fr, fi);
+  }
+}
+
+extern "C" qxd_status qxd_set_gauge(qxd_handle* h, const double* U_phys, const double* A_phys, int on_device,
+                                    void* stream) {
+  if (!h || !U_phys || !A_phys) return QXD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  size_t nU = (size_t)4 * h->Vphys * 18 * sizeof(double);
+  size_t nA = (size_t)4 * h->Vphys * sizeof(double);
+  if (!h->Uphys) {
+    if (hipMalloc(&h->Uphys, nU) != hipSuccess) return QXD_ENOMEM;
+    if (hipMalloc(&h->Aphys, nA) != hipSuccess) return QXD_ENOMEM;
+  }
+  if (on_device) {
+    QXD_HIP(hipMemcpyAsync(h->Uphys, U_phys, nU, hipMemcpyDeviceToDevice, s));
+    QXD_HIP(hipMemcpyAsync(h->Aphys, A_phys, nA, hipMemcpyDeviceToDevice, s));
+  } else {
+    QXD_HIP(hipStreamSynchronize(s));
+    QXD_HIP(hipMemcpy(h->Uphys, U_phys, nU, hipMemcpyHostToDevice));
+    QXD_HIP(hipMemcpy(h->Aphys, A_phys, nA, hipMemcpyHostToDevice));
+  }
+  h->has_gauge = true;
+  h->has_flavour = h->has_clover = h->has_inverse = false;
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_set_flavour(qxd_handle* h, const qxd_flavour* f, void* stream) {
+  if (!h || !f) return QXD_EINVAL;
+  if (!h->has_gauge) return QXD_ESTATE;
+  if (!(f->kappa > 0.0) || !(f->invqel > 0.0)) return QXD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  size_t nl = (size_t)2 * 4 * 9 * h->Ve;
+  if (!h->V64) {
+    if (hipMalloc(&h->V64, nl * sizeof(double2)) != hipSuccess) return QXD_ENOMEM;
+    if (hipMalloc(&h->V32, nl * sizeof(float2)) != hipSuccess) return QXD_ENOMEM;
+    if (hipMalloc(&h->V16, nl * sizeof(uint32_t)) != hipSuccess) return QXD_ENOMEM;
+  }
+  PhysExt pe;
+  for (int m = 0; m < 4; ++m) pe.L[m] = h->g.L[m];
+  // without C* there is no mirror half: x1 never reaches L1
+  pe.Vphys = h->Vphys;
+  int64_t total = 2 * h->Ve * 4;
+  hipLaunchKernelGGL(k_make_links, dim3(div_up(total, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, h->geo, pe,
+                     reinterpret_cast<const double2*>(h->Uphys), h->Aphys, f->qhat, h->V64, h->V32, h->V16);
+  QXD_HIP(hipGetLastError());
+  h->fl = *f;
+  h->has_flavour = true;
+  h->has_clover = h->has_inverse = false;
+  return QXD_OK;
+}

@@ -1,0 +1,345 @@
+// Internal declarations of libqxd (MI355X / gfx950).
+//
+// Device layouts (Ve = half volume, h = half index of a site within its parity):
+//   spinor half field  F64  double2 [12][Ve]      component c = 3 spin + colour
+//                      F32  float4  [6][Ve]       components (2j, 2j+1)
+//                      BF16 uint4   [3][Ve]       components 4j..4j+3, bf16 (re, im)
+//   links V = U z^qhat  [parity][mu][9][Ve] of double2 / float2 / bf16x2 (uint32),
+//                       row-major colour matrix, entry k = 3 row + col
+//   clover blocks       [36][Ve] double2 or [18][Ve] float4 per parity: two
+//                       Hermitian 6x6 blocks (upper, lower chirality), each 36
+//                       reals: 6 real diagonal entries, then the 15 upper
+//                       off-diagonal complex entries (0,1),(0,2),..,(4,5).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "qxd.h"
+
+#define QXD_BLOCK 256
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+
+template <class T>
+struct cx {
+  T re, im;
+};
+
+template <class T>
+__host__ __device__ inline cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <class T>
+__host__ __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T>
+__host__ __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T>
+__host__ __device__ inline cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <class T>
+__host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T>
+__host__ __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <class T>
+__host__ __device__ inline cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+// i * a
+template <class T>
+__host__ __device__ inline cx<T> ti(cx<T> a) { return {-a.im, a.re}; }
+// conj(a) * b
+template <class T>
+__host__ __device__ inline cx<T> cmul_conj(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <class T>
+__host__ __device__ inline T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------------------
+// geometry of the extended lattice (C* orbifold, even-odd half indices)
+
+struct Geo {
+  int Le0, Le1, Le2, Le3;  // extended extents (Le1 = 2 L1 with C*)
+  int L1;                  // physical L1: the shift of a C* boundary crossing in k = 2, 3
+  int cstar;               // 0..3
+  int tanti;               // fermion sign -1 on the time wrap
+  int L3h;                 // Le3 / 2
+  int Ve;                  // half volume
+};
+
+// Coordinates of the site with half index h in parity p.
+__device__ inline void geo_decode(const Geo& g, int p, int h, int& x0, int& x1, int& x2, int& x3) {
+  int x3h = h % g.L3h;
+  int q = h / g.L3h;
+  x2 = q % g.Le2;
+  q /= g.Le2;
+  x1 = q % g.Le1;
+  x0 = q / g.Le1;
+  x3 = 2 * x3h + ((p + x0 + x1 + x2) & 1);
+}
+
+__device__ inline int geo_half(const Geo& g, int x0, int x1, int x2, int x3) {
+  return (x3 >> 1) + g.L3h * (x2 + g.Le2 * (x1 + g.Le1 * x0));
+}
+
+// x1 moved by L1 on the doubled direction (period 2 L1)
+__device__ inline int geo_mirror_x1(const Geo& g, int x1) { return x1 >= g.L1 ? x1 - g.L1 : x1 + g.L1; }
+
+// Half index of the neighbour x + DIR e_MU; *neg set when the hop crosses the
+// antiperiodic time boundary.
+template <int MU, int DIR>
+__device__ inline int geo_nb(const Geo& g, int x0, int x1, int x2, int x3, bool& neg) {
+  neg = false;
+  if (MU == 0) {
+    x0 += DIR;
+    if (x0 < 0) { x0 += g.Le0; neg = g.tanti; }
+    else if (x0 >= g.Le0) { x0 -= g.Le0; neg = g.tanti; }
+  } else if (MU == 1) {
+    x1 += DIR;
+    if (x1 < 0) x1 += g.Le1;
+    else if (x1 >= g.Le1) x1 -= g.Le1;
+  } else if (MU == 2) {
+    x2 += DIR;
+    if (x2 < 0 || x2 >= g.Le2) {
+      x2 = x2 < 0 ? x2 + g.Le2 : x2 - g.Le2;
+      if (g.cstar >= 2) x1 = geo_mirror_x1(g, x1);
+    }
+  } else {
+    x3 += DIR;
+    if (x3 < 0 || x3 >= g.Le3) {
+      x3 = x3 < 0 ? x3 + g.Le3 : x3 - g.Le3;
+      if (g.cstar >= 3) x1 = geo_mirror_x1(g, x1);
+    }
+  }
+  return geo_half(g, x0, x1, x2, x3);
+}
+
+// Spread consecutive workgroups of one XCD over a contiguous range of the
+// lattice: the hardware hands workgroup b to XCD b % 8, so logical tile
+// (b % 8) * ceil-share + b / 8 keeps each XCD's L2 on its own slab.
+__device__ inline int xcd_tile(int b, int G) {
+  int per = G >> 3, rem = G & 7;
+  int xcd = b & 7, idx = b >> 3;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// ---------------------------------------------------------------------------
+// bfloat16 (round to nearest even; NaN kept quiet)
+
+__host__ __device__ inline uint32_t f32_to_bf16_bits(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__host__ __device__ inline float bf16_bits_to_f32(uint32_t b) { return __builtin_bit_cast(float, b << 16); }
+__host__ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  return f32_to_bf16_bits(lo) | (f32_to_bf16_bits(hi) << 16);
+}
+__host__ __device__ inline float bf16lo(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
+__host__ __device__ inline float bf16hi(uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
+
+// ---------------------------------------------------------------------------
+// spinor storage: load / store 12 components of site h
+
+__device__ inline void sp_load(const double2* __restrict__ f, size_t Ve, int h, cx<double> s[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    double2 v = f[c * Ve + h];
+    s[c] = mk(v.x, v.y);
+  }
+}
+__device__ inline void sp_store(double2* __restrict__ f, size_t Ve, int h, const cx<double> s[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) f[c * Ve + h] = make_double2(s[c].re, s[c].im);
+}
+__device__ inline void sp_load(const float4* __restrict__ f, size_t Ve, int h, cx<float> s[12]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    float4 v = f[j * Ve + h];
+    s[2 * j] = mk(v.x, v.y);
+    s[2 * j + 1] = mk(v.z, v.w);
+  }
+}
+__device__ inline void sp_store(float4* __restrict__ f, size_t Ve, int h, const cx<float> s[12]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    f[j * Ve + h] = make_float4(s[2 * j].re, s[2 * j].im, s[2 * j + 1].re, s[2 * j + 1].im);
+}
+__device__ inline void sp_load(const uint4* __restrict__ f, size_t Ve, int h, cx<float> s[12]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    uint4 v = f[j * Ve + h];
+    s[4 * j + 0] = mk(bf16lo(v.x), bf16hi(v.x));
+    s[4 * j + 1] = mk(bf16lo(v.y), bf16hi(v.y));
+    s[4 * j + 2] = mk(bf16lo(v.z), bf16hi(v.z));
+    s[4 * j + 3] = mk(bf16lo(v.w), bf16hi(v.w));
+  }
+}
+__device__ inline void sp_store(uint4* __restrict__ f, size_t Ve, int h, const cx<float> s[12]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    uint4 v;
+    v.x = pack_bf16x2(s[4 * j].re, s[4 * j].im);
+    v.y = pack_bf16x2(s[4 * j + 1].re, s[4 * j + 1].im);
+    v.z = pack_bf16x2(s[4 * j + 2].re, s[4 * j + 2].im);
+    v.w = pack_bf16x2(s[4 * j + 3].re, s[4 * j + 3].im);
+    f[j * Ve + h] = v;
+  }
+}
+
+// link storage: 9 entries of the colour matrix of link (parity array, mu, h)
+__device__ inline void lk_load(const double2* __restrict__ V, size_t Ve, int mu, int h, cx<double> u[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double2 v = V[(mu * 9 + k) * Ve + h];
+    u[k] = mk(v.x, v.y);
+  }
+}
+__device__ inline void lk_load(const float2* __restrict__ V, size_t Ve, int mu, int h, cx<float> u[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    float2 v = V[(mu * 9 + k) * Ve + h];
+    u[k] = mk(v.x, v.y);
+  }
+}
+__device__ inline void lk_load(const uint32_t* __restrict__ V, size_t Ve, int mu, int h, cx<float> u[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    uint32_t v = V[(mu * 9 + k) * Ve + h];
+    u[k] = mk(bf16lo(v), bf16hi(v));
+  }
+}
+
+// clover storage: two packed Hermitian 6x6 blocks (72 reals)
+__device__ inline void cl_load(const double2* __restrict__ C, size_t Ve, int h, double r[72]) {
+#pragma unroll
+  for (int k = 0; k < 36; ++k) {
+    double2 v = C[k * Ve + h];
+    r[2 * k] = v.x;
+    r[2 * k + 1] = v.y;
+  }
+}
+__device__ inline void cl_load(const float4* __restrict__ C, size_t Ve, int h, float r[72]) {
+#pragma unroll
+  for (int k = 0; k < 18; ++k) {
+    float4 v = C[k * Ve + h];
+    r[4 * k] = v.x;
+    r[4 * k + 1] = v.y;
+    r[4 * k + 2] = v.z;
+    r[4 * k + 3] = v.w;
+  }
+}
+
+// out[0..5] = H in[0..5] for one packed Hermitian block b (36 reals)
+template <class T>
+__device__ inline void herm6_mul(const T* b, const cx<T>* in, cx<T>* out) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) out[i] = b[i] * in[i];
+  int k = 6;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j) {
+      cx<T> hij = mk(b[k], b[k + 1]);
+      k += 2;
+      out[i] = out[i] + hij * in[j];
+      out[j] = out[j] + cmul_conj(hij, in[i]);
+    }
+  }
+}
+
+// index of the packed entry (i, j), i < j, within a block
+__host__ __device__ constexpr int herm6_off(int i, int j) {
+  // entries before row i: sum_{r<i} (5 - r)
+  return 6 + 2 * (i * 5 - i * (i - 1) / 2 + (j - i - 1));
+}
+
+// ---------------------------------------------------------------------------
+// the handle
+
+struct qxd_handle {
+  int device = 0;
+  qxd_geom g{};
+  Geo geo{};
+  int64_t V = 0, Ve = 0, Vphys = 0;
+  // gauge field on the physical lattice (canonical layout)
+  double* Uphys = nullptr;  // [4][Vphys][9] complex
+  double* Aphys = nullptr;  // [4][Vphys]
+  bool has_gauge = false, has_flavour = false, has_clover = false, has_inverse = false;
+  qxd_flavour fl{};
+  // combined links V = U z^qhat, [2][4][9][Ve]
+  double2* V64 = nullptr;
+  float2* V32 = nullptr;
+  uint32_t* V16 = nullptr;
+  // clover blocks: H on even and odd sites, H^-1 on odd sites
+  double2 *He64 = nullptr, *Ho64 = nullptr, *Hi64 = nullptr;
+  float4 *He32 = nullptr, *Ho32 = nullptr, *Hi32 = nullptr;
+  // odd half-field workspaces for the Schur passes
+  double2* t64 = nullptr;
+  float4* t32 = nullptr;
+  uint4* t16 = nullptr;
+  // reductions
+  double* partial = nullptr;  // [QXD_MAX_PARTIAL]
+  double* scal = nullptr;     // [QXD_NSCAL] device scalars
+  double* scal_host = nullptr;  // pinned mirror
+  size_t npartial = 0;        // doubles in `partial`
+  // solver workspaces (grow-only), indexed by role
+  void* ws[64] = {};
+  size_t ws_bytes[64] = {};
+};
+
+#define QXD_NSCAL 4096
+#define QXD_MAX_PARTIAL (64 * 2048)
+
+// device scalar slots
+enum {
+  S_ZZ0 = 0, S_ZZ1 = 1, S_WW = 2, S_RR = 3, S_NB = 4, S_RT = 5, S_BH = 6, S_ONE = 7,
+  S_FRR = 16,            // FGCR |r|^2
+  S_FB = 32,             // FGCR |chi_k|^2, k < 64
+  S_FC = 128,            // FGCR c_k (complex), k < 64
+  S_FR = 1024,           // FGCR R[k][j] (complex), column k at S_FR + 2 k QXD_MAXKV_R
+  S_FAL = 3200,          // FGCR solution coefficients (complex)
+  S_NN = 3400            // network preconditioner scratch scalars
+};
+#define QXD_MAXKV_R 32
+
+// grow-only device workspace number i of at least `bytes`
+inline void* ws_get(qxd_handle* h, int i, size_t bytes) {
+  if (h->ws_bytes[i] >= bytes) return h->ws[i];
+  if (h->ws[i]) (void)hipFree(h->ws[i]);
+  h->ws[i] = nullptr;
+  h->ws_bytes[i] = 0;
+  if (hipMalloc(&h->ws[i], bytes) != hipSuccess) return nullptr;
+  h->ws_bytes[i] = bytes;
+  return h->ws[i];
+}
+
+struct qxd_nn;
+
+// error helpers
+#define QXD_HIP(call)                            \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return QXD_EHIP;       \
+  } while (0)
+
+#define QXD_TRY(call)                            \
+  do {                                           \
+    qxd_status s_ = (call);                      \
+    if (s_ != QXD_OK) return s_;                 \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// internal entry points shared between translation units
+// out[v] = sum_{i<n} partial[v * stride + i] for v < nvals, summed in a fixed order
+void launch_final_sum(const double* partial, int n, int nvals, int stride, double* out, hipStream_t s);
+qxd_status qxd_schur_apply(qxd_handle* h, qxd_prec p, int dagger, void* out_e, const void* in_e, double* norm_slot,
+                           hipStream_t s);
+qxd_status nn_apply_internal(qxd_handle* h, qxd_nn* net, float4* out_e, const float4* in_e, hipStream_t s);
+qxd_status qxd_schur_apply_mixed(qxd_handle* h, int dagger, float4* out_e, const float4* in_e, double* norm_slot,
+                                 hipStream_t s);

@@ -1,0 +1,152 @@
+"""GPU parity of the operator entry points against the FP64 oracle.
+
+Bars: FP64 1e-13 relative (max-abs error over max-abs value), FP32 1e-6 relative
+in norm, BF16 storage reported and loosely gated; pack/unpack bit-exact."""
+import numpy as np
+import pytest
+
+import synthgen as sg
+from tests.gpu_common import even_only, make_pair, norm_err, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+qxd = pytest.importorskip("paper_1908_11673_amd")
+
+FD, FU = sg.FLAVOURS["d"], sg.FLAVOURS["u"]
+
+# several tiles, ragged tails (Ve not a multiple of 256), every cstar, both time signs
+GEOMS = [
+    ((8, 4, 4, 4), 1, False),      # the 8 x 8 x 4 x 4 extended lattice of the small solve workload
+    ((6, 4, 6, 2), 0, False),
+    ((4, 6, 2, 6), 2, True),
+    ((6, 2, 6, 4), 3, False),
+    ((4, 4, 4, 6), 3, True),
+    ((2, 2, 2, 2), 3, False),
+]
+
+
+@pytest.fixture(scope="module", params=GEOMS, ids=lambda g: "L%s_cs%d_t%d" % ("x".join(map(str, g[0])), g[1], g[2]))
+def pair(request):
+    L, cstar, tanti = request.param
+    o, lat, st = make_pair(L, cstar, FD, sigma=0.3, su1=0.4, seed=17, tanti=tanti)
+    yield o, lat, st
+    lat.close()
+
+
+def test_pack_unpack_roundtrip_is_exact(pair):
+    o, lat, _ = pair
+    psi = sg.spinor(5, o.V)
+    d = to_dev(psi)
+    for prec in (qxd.F64,):
+        back = lat.unpack(lat.pack(d, prec), prec).cpu().numpy()
+        assert np.array_equal(back, psi)
+    # FP32 round trip equals rounding to complex64
+    back = lat.unpack(lat.pack(d, qxd.F32), qxd.F32).cpu().numpy()
+    assert np.array_equal(back, psi.astype(np.complex64).astype(np.complex128))
+
+
+def test_dw_apply_f64(pair):
+    o, lat, _ = pair
+    psi = sg.spinor(11, o.V)
+    out = lat.field(qxd.F64, full=True)
+    qxd.qxd_dw_apply(lat.h, qxd.F64, out, lat.pack(to_dev(psi)))
+    got = lat.unpack(out).cpu().numpy()
+    assert rel_err(got, o.dirac(psi)) < 1e-13
+
+
+@pytest.mark.parametrize("L,cstar", [((4, 4, 2, 6), 3), ((6, 2, 4, 4), 2)])
+def test_up_flavour_dw_and_schur_f64(L, cstar):
+    o, lat, _ = make_pair(L, cstar, FU, sigma=0.3, su1=0.4, seed=23)
+    psi = sg.spinor(21, o.V)
+    out = lat.field(qxd.F64, full=True)
+    qxd.qxd_dw_apply(lat.h, qxd.F64, out, lat.pack(to_dev(psi)))
+    assert rel_err(lat.unpack(out).cpu().numpy(), o.dirac(psi)) < 1e-13
+    pe = even_only(o, psi)
+    x = lat.pack(to_dev(pe))
+    qxd.qxd_dw_eo_schur(lat.h, qxd.F64, 0, out[:12 * lat.Ve], x[:12 * lat.Ve])
+    assert rel_err(lat.unpack(out).cpu().numpy(), o.schur(pe)) < 1e-13
+    lat.close()
+
+
+@pytest.mark.parametrize("dagger", [False, True])
+def test_schur_f64(pair, dagger):
+    o, lat, _ = pair
+    psi = even_only(o, sg.spinor(12, o.V))
+    x = lat.pack(to_dev(psi))
+    out = lat.field(qxd.F64, full=True)
+    qxd.qxd_dw_eo_schur(lat.h, qxd.F64, dagger, out[:12 * lat.Ve], x[:12 * lat.Ve])
+    got = lat.unpack(out).cpu().numpy()
+    want = o.schur(psi, dagger=dagger)
+    assert rel_err(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("dagger", [False, True])
+def test_schur_f32(pair, dagger):
+    o, lat, _ = pair
+    psi = even_only(o, sg.spinor(13, o.V))
+    x = lat.pack(to_dev(psi), qxd.F32)
+    out = lat.field(qxd.F32, full=True)
+    qxd.qxd_dw_eo_schur(lat.h, qxd.F32, dagger, out[:12 * lat.Ve], x[:12 * lat.Ve])
+    got = lat.unpack(out, qxd.F32).cpu().numpy()
+    want = o.schur(psi, dagger=dagger)
+    assert norm_err(got, want) < 1e-6
+    assert rel_err(got, want) < 5e-6
+
+
+def test_schur_bf16_storage_error_is_bounded(pair):
+    o, lat, _ = pair
+    psi = even_only(o, sg.spinor(14, o.V))
+    x = lat.pack(to_dev(psi), qxd.BF16)
+    out = lat.field(qxd.BF16, full=True)
+    qxd.qxd_dw_eo_schur(lat.h, qxd.BF16, False, out[:24 * lat.Ve], x[:24 * lat.Ve])
+    got = lat.unpack(out, qxd.BF16).cpu().numpy()
+    want = o.schur(psi)
+    err = norm_err(got, want)
+    print("bf16 storage relative error %.3e" % err)
+    assert err < 2e-2
+
+
+def test_dw_apply_f32(pair):
+    o, lat, _ = pair
+    psi = sg.spinor(15, o.V)
+    out = lat.field(qxd.F32, full=True)
+    qxd.qxd_dw_apply(lat.h, qxd.F32, out, lat.pack(to_dev(psi), qxd.F32))
+    got = lat.unpack(out, qxd.F32).cpu().numpy()
+    assert norm_err(got, o.dirac(psi)) < 1e-6
+
+
+def test_eo_source_and_reconstruct(pair):
+    o, lat, _ = pair
+    b = sg.spinor(16, o.V)
+    bd = lat.pack(to_dev(b))
+    bh = lat.field(qxd.F64, full=True)
+    qxd.qxd_eo_source(lat.h, bh[:12 * lat.Ve], bd)
+    assert rel_err(lat.unpack(bh).cpu().numpy(), o.eo_source(b)) < 1e-13
+    xe = even_only(o, sg.spinor(18, o.V))
+    x = lat.field(qxd.F64, full=True)
+    qxd.qxd_eo_reconstruct(lat.h, x, lat.pack(to_dev(xe))[:12 * lat.Ve], bd)
+    assert rel_err(lat.unpack(x).cpu().numpy(), o.eo_reconstruct(xe, b)) < 1e-13
+
+
+def test_schur_is_deterministic(pair):
+    o, lat, _ = pair
+    psi = even_only(o, sg.spinor(19, o.V))
+    x = lat.pack(to_dev(psi))
+    a = lat.field(qxd.F64, full=True)
+    b = lat.field(qxd.F64, full=True)
+    qxd.qxd_dw_eo_schur(lat.h, qxd.F64, 0, a[:12 * lat.Ve], x[:12 * lat.Ve])
+    qxd.qxd_dw_eo_schur(lat.h, qxd.F64, 0, b[:12 * lat.Ve], x[:12 * lat.Ve])
+    assert torch.equal(a, b)
+
+
+def test_invalid_arguments_are_rejected():
+    lat = qxd.Lattice((4, 4, 4, 4), 3)
+    f = lat.field(qxd.F64)
+    with pytest.raises(qxd.QxdError) as e:  # operator before the clover inverse exists
+        qxd.qxd_dw_eo_schur(lat.h, qxd.F64, 0, f, lat.field(qxd.F64))
+    assert e.value.code == 8
+    with pytest.raises(qxd.QxdError) as e:  # in place
+        qxd.qxd_dw_eo_schur(lat.h, qxd.F64, 0, f, f)
+    assert e.value.code == 1
+    lat.close()

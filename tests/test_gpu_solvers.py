@@ -1,0 +1,106 @@
+"""GPU solves through the C ABI: FP64 true residual 1e-10 on the full lattice,
+checked independently by the oracle, and the solution compared with the
+oracle's own CG solution; failure statuses forced from the host."""
+import numpy as np
+import pytest
+
+import oracle
+import synthgen as sg
+from tests.gpu_common import make_pair, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+qxd = pytest.importorskip("paper_1908_11673_amd")
+
+W0 = sg.WORKLOADS["c0"]
+FD, FU = sg.FLAVOURS["d"], sg.FLAVOURS["u"]
+
+
+@pytest.fixture(scope="module")
+def c0():
+    o, lat, st = make_pair(W0["L"], W0["cstar"], FD, sigma=W0["sigma_su3"], su1=W0["sigma_u1"],
+                           seed=W0["gauge_seed"])
+    b = sg.spinor(W0["source_seed"], o.V)
+    nb = np.linalg.norm(b)
+    xe, it, _ = o.cg(o.eo_source(b), 1e-12 * nb)
+    x_ref = o.eo_reconstruct(xe, b)
+    yield o, lat, b, x_ref
+    lat.close()
+
+
+def _check_solution(o, b, x, x_ref, tag):
+    res = np.linalg.norm(b - o.dirac(x)) / np.linalg.norm(b)
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    print("%s: oracle true residual %.3e, |x - x_oracle|/|x_oracle| %.3e" % (tag, res, err))
+    assert res <= 1e-10
+    assert err <= 1e-8
+
+
+def test_cg_f64_c0(c0):
+    o, lat, b, x_ref = c0
+    bd = lat.pack(to_dev(b))
+    x = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10), x, bd)
+    print(st)
+    assert st["status"] == 0 and st["true_residual"] <= 1e-10
+    _check_solution(o, b, lat.unpack(x).cpu().numpy(), x_ref, "cg")
+
+
+@pytest.mark.parametrize("inner", [qxd.F64, qxd.F32, qxd.BF16], ids=["f64", "f32", "bf16links"])
+def test_fgcr_c0(c0, inner):
+    o, lat, b, x_ref = c0
+    bd = lat.pack(to_dev(b))
+    x = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner, nkv=16), None, x, bd)
+    print(st)
+    assert st["status"] == 0 and st["true_residual"] <= 1e-10
+    _check_solution(o, b, lat.unpack(x).cpu().numpy(), x_ref, "fgcr%d" % inner)
+
+
+def test_solves_are_deterministic(c0):
+    o, lat, b, _ = c0
+    bd = lat.pack(to_dev(b))
+    xs = []
+    for _ in range(2):
+        x = lat.field(qxd.F64, full=True)
+        qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32), None, x, bd)
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1])
+
+
+def test_enoconv_when_iteration_limit_hit(c0):
+    o, lat, b, _ = c0
+    x = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(nmx=1, res=1e-10), x, lat.pack(to_dev(b)), check=False)
+    assert st["status"] == 6
+    st = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(nmx=1, res=1e-10), None, x, lat.pack(to_dev(b)), check=False)
+    assert st["status"] == 6
+
+
+def test_enan_on_nan_source(c0):
+    o, lat, b, _ = c0
+    bb = b.copy()
+    bb[3, 1, 2] = np.nan
+    x = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(), x, lat.pack(to_dev(bb)), check=False)
+    assert st["status"] == 5
+    st = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(), None, x, lat.pack(to_dev(bb)), check=False)
+    assert st["status"] == 5
+
+
+def test_esingular_on_exactly_singular_clover():
+    """U = 1 and one U(1) link at pi/2: the SW term at x0 + nu is -(u1csw qhat / 8) sigma_{0 nu};
+    with u1csw = 32, qhat = 1, kappa = 1/8 one eigenvalue of the block is exactly zero."""
+    L = (4, 4, 4, 4)
+    lat = qxd.Lattice(L, 0)
+    Vp = 4 ** 4
+    U = np.broadcast_to(np.eye(3, dtype=complex), (4, Vp, 3, 3)).copy()
+    A = np.zeros((4, Vp))
+    A[0, 0] = np.pi / 2
+    qxd.qxd_set_gauge(lat.h, U, A)
+    qxd.qxd_set_flavour(lat.h, qhat=1, invqel=1.0, kappa=0.125, su3csw=0.0, u1csw=32.0)
+    qxd.qxd_clover_build(lat.h)
+    st = qxd.qxd_clover_invert(lat.h, check=False)
+    assert st["status"] == 4 and st["n_singular"] >= 1
+    lat.close()
