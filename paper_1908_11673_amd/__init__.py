@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libqxd.so")
+_LIB_PATH = os.environ.get("QXD_LIBRARY", os.path.join(_HERE, "libqxd.so"))
 
 F64, F32, BF16 = 0, 1, 2
 PRECOND_NONE, PRECOND_NN = 0, 1

@@ -53,6 +53,8 @@ extern "C" qxd_status qxd_create(const qxd_geom* g, qxd_handle** out) {
   h->geo.tanti = g->t_antiperiodic ? 1 : 0;
   h->geo.L3h = g->L[3] / 2;
   h->geo.Ve = (int)h->Ve;
+  h->geo.tchunk = 8;
+  if (const char* e = std::getenv("QXD_TILE_CHUNK")) h->geo.tchunk = std::atoi(e);
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return QXD_EHIP;

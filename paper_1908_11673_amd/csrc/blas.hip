@@ -226,25 +226,29 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_zero(VT* __restrict__ x, size_t n
   GRID_STRIDE(i, n) x[i] = VT{};
 }
 
-// d (FP32, n2 words = 2 complex each) = s / sqrt(scal[i])  (s FP64)
-__global__ __launch_bounds__(QXD_BLOCK) void k_down(float4* __restrict__ d, const double2* __restrict__ s, size_t nw,
+// FP64 half field [12][Ve] double2 -> FP32 half field [6][Ve] float4: word
+// j Ve + h holds components 2j and 2j+1 of site h.
+// d = s / sqrt(scal[i_n2])
+__global__ __launch_bounds__(QXD_BLOCK) void k_down(float4* __restrict__ d, const double2* __restrict__ s, size_t Ve,
                                                     const double* __restrict__ scal, int i_n2) {
   double sc = 1.0 / sqrt(scal[i_n2]);
-  GRID_STRIDE(i, nw) {
-    double2 a = s[2 * i], b = s[2 * i + 1];
+  GRID_STRIDE(i, 6 * Ve) {
+    size_t j = i / Ve, h = i - j * Ve;
+    double2 a = s[(2 * j) * Ve + h], b = s[(2 * j + 1) * Ve + h];
     d[i] = make_float4((float)(sc * a.x), (float)(sc * a.y), (float)(sc * b.x), (float)(sc * b.y));
   }
 }
 
-// x (FP64) += sqrt(scal[i]) e (FP32)
-__global__ __launch_bounds__(QXD_BLOCK) void k_up_acc(double2* __restrict__ x, const float4* __restrict__ e, size_t nw,
+// x (FP64) += sqrt(scal[i]) e (FP32), same component map as k_down
+__global__ __launch_bounds__(QXD_BLOCK) void k_up_acc(double2* __restrict__ x, const float4* __restrict__ e, size_t Ve,
                                                       const double* __restrict__ scal, int i_n2) {
   double sc = sqrt(scal[i_n2]);
-  GRID_STRIDE(i, nw) {
+  GRID_STRIDE(i, 6 * Ve) {
+    size_t j = i / Ve, h = i - j * Ve;
     float4 v = e[i];
-    double2 a = x[2 * i], b = x[2 * i + 1];
-    x[2 * i] = make_double2(a.x + sc * (double)v.x, a.y + sc * (double)v.y);
-    x[2 * i + 1] = make_double2(b.x + sc * (double)v.z, b.y + sc * (double)v.w);
+    double2 a = x[(2 * j) * Ve + h], b = x[(2 * j + 1) * Ve + h];
+    x[(2 * j) * Ve + h] = make_double2(a.x + sc * (double)v.x, a.y + sc * (double)v.y);
+    x[(2 * j + 1) * Ve + h] = make_double2(b.x + sc * (double)v.z, b.y + sc * (double)v.w);
   }
 }
 
@@ -309,11 +313,11 @@ template <class VT>
 void blas_zero(VT* x, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, n);
 }
-void blas_down(qxd_handle* h, float4* d, const double2* src, size_t nw, int i_n2, hipStream_t s) {
-  hipLaunchKernelGGL(k_down, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, d, src, nw, h->scal, i_n2);
+void blas_down(qxd_handle* h, float4* d, const double2* src, int i_n2, hipStream_t s) {
+  hipLaunchKernelGGL(k_down, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, d, src, (size_t)h->Ve, h->scal, i_n2);
 }
-void blas_up_acc(qxd_handle* h, double2* x, const float4* e, size_t nw, int i_n2, hipStream_t s) {
-  hipLaunchKernelGGL(k_up_acc, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, e, nw, h->scal, i_n2);
+void blas_up_acc(qxd_handle* h, double2* x, const float4* e, int i_n2, hipStream_t s) {
+  hipLaunchKernelGGL(k_up_acc, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, e, (size_t)h->Ve, h->scal, i_n2);
 }
 
 #define INST(VT)                                                                                        \

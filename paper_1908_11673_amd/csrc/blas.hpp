@@ -29,5 +29,6 @@ template <class VT> void blas_r_update(qxd_handle* h, VT* r, const VT* v, size_t
 template <class VT>
 void blas_multi_axpy(qxd_handle* h, VT* x, const Ptrs& basis, int k, const double* coef, size_t n, hipStream_t s);
 template <class VT> void blas_zero(VT* x, size_t n, hipStream_t s);
-void blas_down(qxd_handle* h, float4* d, const double2* src, size_t nw, int i_n2, hipStream_t s);
-void blas_up_acc(qxd_handle* h, double2* x, const float4* e, size_t nw, int i_n2, hipStream_t s);
+// FP64 half field <-> FP32 half field (the layouts interleave components differently)
+void blas_down(qxd_handle* h, float4* d, const double2* src, int i_n2, hipStream_t s);
+void blas_up_acc(qxd_handle* h, double2* x, const float4* e, int i_n2, hipStream_t s);

@@ -146,7 +146,7 @@ template <class T, class SPT, class LKT, class CLT, bool DAG>
 __global__ __launch_bounds__(QXD_BLOCK) void k_schur1(Geo g, const SPT* __restrict__ in_e, SPT* __restrict__ t_o,
                                                       const LKT* __restrict__ Ve_l, const LKT* __restrict__ Vo_l,
                                                       const CLT* __restrict__ Hi) {
-  int h = xcd_tile(blockIdx.x, gridDim.x) * QXD_BLOCK + threadIdx.x;
+  int h = site_tile(blockIdx.x, gridDim.x, g.tchunk) * QXD_BLOCK + threadIdx.x;
   if (h >= g.Ve) return;
   cx<T> acc[12], out[12];
   hop_site<DAG, T>(g, 1, h, in_e, Vo_l, Ve_l, acc);
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_schur2(Geo g, const SPT* __restri
                                                       const LKT* __restrict__ Ve_l, const LKT* __restrict__ Vo_l,
                                                       const CLT* __restrict__ He, double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  int tile = site_tile(blockIdx.x, gridDim.x, g.tchunk);
   int h = tile * QXD_BLOCK + threadIdx.x;
   double n2 = 0.0;
   if (h < g.Ve) {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_dw(Geo g, int p, const SPT* __res
                                                   const SPT* __restrict__ in_q, SPT* __restrict__ out_p,
                                                   const LKT* __restrict__ Vp, const LKT* __restrict__ Vq,
                                                   const CLT* __restrict__ Hp) {
-  int h = xcd_tile(blockIdx.x, gridDim.x) * QXD_BLOCK + threadIdx.x;
+  int h = site_tile(blockIdx.x, gridDim.x, g.tchunk) * QXD_BLOCK + threadIdx.x;
   if (h >= g.Ve) return;
   cx<T> acc[12], s[12], c[12];
   hop_site<false, T>(g, p, h, in_q, Vp, Vq, acc);
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_hop_add(Geo g, int p, const doubl
                                                        const double2* __restrict__ base, double2* __restrict__ out,
                                                        const double2* __restrict__ Vp, const double2* __restrict__ Vq,
                                                        const double2* __restrict__ C, double alpha) {
-  int h = xcd_tile(blockIdx.x, gridDim.x) * QXD_BLOCK + threadIdx.x;
+  int h = site_tile(blockIdx.x, gridDim.x, g.tchunk) * QXD_BLOCK + threadIdx.x;
   if (h >= g.Ve) return;
   cx<double> acc[12], s[12], c[12];
   hop_site<false, double>(g, p, h, in_q, Vp, Vq, acc);

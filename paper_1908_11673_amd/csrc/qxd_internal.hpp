@@ -66,6 +66,7 @@ struct Geo {
   int tanti;               // fermion sign -1 on the time wrap
   int L3h;                 // Le3 / 2
   int Ve;                  // half volume
+  int tchunk;              // workgroup -> lattice tile order (see site_tile)
 };
 
 // Coordinates of the site with half index h in parity p.
@@ -115,13 +116,25 @@ __device__ inline int geo_nb(const Geo& g, int x0, int x1, int x2, int x3, bool&
   return geo_half(g, x0, x1, x2, x3);
 }
 
-// Spread consecutive workgroups of one XCD over a contiguous range of the
-// lattice: the hardware hands workgroup b to XCD b % 8, so logical tile
-// (b % 8) * ceil-share + b / 8 keeps each XCD's L2 on its own slab.
-__device__ inline int xcd_tile(int b, int G) {
-  int per = G >> 3, rem = G & 7;
-  int xcd = b & 7, idx = b >> 3;
-  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+// Order in which workgroups walk the lattice.  The hardware hands workgroup b
+// to XCD b % 8.  With tchunk = K > 0 the walk proceeds in windows of 8K
+// consecutive tiles; inside a window each XCD takes K consecutive tiles, so the
+// spatial neighbours of a tile mostly sit in the same XCD's L2, while the whole
+// GPU advances through the lattice together and the time-direction neighbours
+// (two time slices apart) are still in the last-level cache when read again.
+// tchunk = 0: plain order; tchunk < 0: each XCD owns one contiguous eighth.
+__device__ inline int site_tile(int b, int G, int K) {
+  if (K == 0) return b;
+  if (K < 0) {
+    int per = G >> 3, rem = G & 7;
+    int xcd = b & 7, idx = b >> 3;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  }
+  int win = 8 * K;
+  int w = b / win;
+  if ((w + 1) * win > G) return b;  // ragged last window: plain order
+  int r = b - w * win;
+  return w * win + (r & 7) * K + (r >> 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -190,24 +203,44 @@ __device__ inline void sp_store(uint4* __restrict__ f, size_t Ve, int h, const c
 }
 
 // link storage: 9 entries of the colour matrix of link (parity array, mu, h)
+// Links and clover blocks are read once per pass: load them with the
+// non-temporal hint so that they do not evict the neighbour spinors, which are
+// read by up to eight sites, from the L2.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ inline double2 ld_stream(const double2* p) {
+  nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ inline float2 ld_stream(const float2* p) {
+  nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ inline float4 ld_stream(const float4* p) {
+  nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline uint32_t ld_stream(const uint32_t* p) { return __builtin_nontemporal_load(p); }
+
 __device__ inline void lk_load(const double2* __restrict__ V, size_t Ve, int mu, int h, cx<double> u[9]) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    double2 v = V[(mu * 9 + k) * Ve + h];
+    double2 v = ld_stream(&V[(mu * 9 + k) * Ve + h]);
     u[k] = mk(v.x, v.y);
   }
 }
 __device__ inline void lk_load(const float2* __restrict__ V, size_t Ve, int mu, int h, cx<float> u[9]) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    float2 v = V[(mu * 9 + k) * Ve + h];
+    float2 v = ld_stream(&V[(mu * 9 + k) * Ve + h]);
     u[k] = mk(v.x, v.y);
   }
 }
 __device__ inline void lk_load(const uint32_t* __restrict__ V, size_t Ve, int mu, int h, cx<float> u[9]) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    uint32_t v = V[(mu * 9 + k) * Ve + h];
+    uint32_t v = ld_stream(&V[(mu * 9 + k) * Ve + h]);
     u[k] = mk(bf16lo(v), bf16hi(v));
   }
 }
@@ -216,7 +249,7 @@ __device__ inline void lk_load(const uint32_t* __restrict__ V, size_t Ve, int mu
 __device__ inline void cl_load(const double2* __restrict__ C, size_t Ve, int h, double r[72]) {
 #pragma unroll
   for (int k = 0; k < 36; ++k) {
-    double2 v = C[k * Ve + h];
+    double2 v = ld_stream(&C[k * Ve + h]);
     r[2 * k] = v.x;
     r[2 * k + 1] = v.y;
   }
@@ -224,7 +257,7 @@ __device__ inline void cl_load(const double2* __restrict__ C, size_t Ve, int h, 
 __device__ inline void cl_load(const float4* __restrict__ C, size_t Ve, int h, float r[72]) {
 #pragma unroll
   for (int k = 0; k < 18; ++k) {
-    float4 v = C[k * Ve + h];
+    float4 v = ld_stream(&C[k * Ve + h]);
     r[4 * k] = v.x;
     r[4 * k + 1] = v.y;
     r[4 * k + 2] = v.z;

@@ -325,11 +325,11 @@ extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm
       blas_multi_axpy<double2>(h, xe, pe, 1, h->scal + S_FAL, n64, s);
     } else {
       // FP32 inner solve of D_hat e = r / |r|, then x += |r| e
-      blas_down(h, r32, r, n32, S_RR, s);
+      blas_down(h, r32, r, S_RR, s);
       double itol = std::fmax(inner_res, 0.5 * tol / rn);
       ic = fgcr<float4>(h, op, net, fallback_after, e32, r32, n32, nkv, itol, steps_left, &fr, s);
       if (ic != QXD_OK) { rc = ic; break; }
-      blas_up_acc(h, xe, e32, n32, S_RR, s);
+      blas_up_acc(h, xe, e32, S_RR, s);
     }
     st.inner_it += fr.steps;
     st.schur_applies += fr.applies;
