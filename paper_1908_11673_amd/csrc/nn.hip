@@ -1,22 +1,611 @@
-// Network preconditioner (filled in below the Dirac path).
-#include "qxd_internal.hpp"
+// Learned preconditioner: three 3^4-tap convolutions on the extended lattice
+// (taps follow the C* neighbour map: x + d is the composition of unit steps in
+// directions 0..3), real channels 24 -> 32 -> 32 -> 24, no biases, ReLU after
+// layers 1 and 2; M(r) = |r| N(r / |r|) on even half fields.
+//
+// Each layer is an implicit GEMM  out[site][cout] = sum_{tap, cin} in[site + d][cin] W[tap][cout][cin]
+// on bf16 MFMA with FP32 accumulation: a wave owns 64 consecutive sites and all
+// 32 output channels (4 x 2 tiles of v_mfma_f32_16x16x32_bf16 per tap); each
+// lane gathers the 8 input channels it feeds to the matrix core with one
+// 16-byte load from the neighbour's channel vector.  Activations are stored as
+// [site][32] bf16 (layer-1 input and layer-3 output padded from 24 channels);
+// sites are numbered parity-major (even half first), so layer 3 runs on the
+// even sites only and writes the spinor layout directly.
+//
+// Training: the data gradient of a convolution is the convolution with the
+// transposed weights on the reversed taps (x + d = z  <=>  x = z - d); the
+// weight gradient sum_x g[x][cout] in[x + d][cin] is a GEMM over sites, computed
+// on v_mfma_f32_32x32x16_bf16 from tiles transposed through LDS, with per-chunk
+// partial sums reduced in a fixed order.  FP32 master weights, Adam.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "blas.hpp"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+#define NN_C 32
+#define NN_TAPS 81
+#define NN_LAYER_W (NN_TAPS * NN_C * NN_C)  // padded bf16 weights per layer
+
+static const int kCin[3] = {24, 32, 32};
+static const int kCout[3] = {32, 32, 24};
+static const int kOff[3] = {0, 81 * 32 * 24, 81 * 32 * 24 + 81 * 32 * 32};
 
 struct qxd_nn {
-  qxd_handle* h;
+  qxd_handle* h = nullptr;
+  float* w = nullptr;      // FP32 master weights (packed as in the header)
+  uint16_t* wf = nullptr;  // bf16 forward weights [3][81][32 cout][32 cin]
+  uint16_t* wa = nullptr;  // bf16 adjoint weights [3][81 reversed][32 cin][32 cout]
+  float *m = nullptr, *v = nullptr, *grad = nullptr;
+  int64_t t = 0;
+  uint16_t *a0 = nullptr, *a1 = nullptr, *a2 = nullptr;  // [V][32]
+  uint16_t *g3 = nullptr, *gA = nullptr, *gB = nullptr;  // training: [V][32]
+  float* y = nullptr;      // training: raw network output (even half field, F32)
+  float* part = nullptr;   // weight-gradient partials
+  int nchunk = 0;
 };
 
-qxd_status nn_apply_internal(qxd_handle*, qxd_nn*, float4*, const float4*, hipStream_t) { return QXD_EINVAL; }
+static const int kWgChunk = 2048;  // sites per weight-gradient workgroup
 
-extern "C" qxd_status qxd_nn_create(qxd_handle*, qxd_nn**) { return QXD_EINVAL; }
-extern "C" qxd_status qxd_nn_destroy(qxd_nn*) { return QXD_EINVAL; }
-extern "C" qxd_status qxd_nn_set_weights(qxd_nn*, const float*) { return QXD_EINVAL; }
-extern "C" qxd_status qxd_nn_get_weights(qxd_nn*, float*) { return QXD_EINVAL; }
-extern "C" qxd_status qxd_nn_apply(qxd_handle*, qxd_nn*, void*, const void*, void*) { return QXD_EINVAL; }
-extern "C" qxd_status qxd_nn_loss_grad(qxd_handle*, qxd_nn*, const void*, const void*, int, double*, float*, void*) {
-  return QXD_EINVAL;
+__device__ inline uint16_t f2bf(float f) { return (uint16_t)f32_to_bf16_bits(f); }
+__device__ inline float bf2f(uint16_t b) { return bf16_bits_to_f32(b); }
+
+// unit step of coordinates along mu (C* shift of x1 across the k <= cstar boundaries)
+__device__ inline void nn_step(const Geo& g, int* x, int mu, int dir) {
+  int Le = mu == 0 ? g.Le0 : mu == 1 ? g.Le1 : mu == 2 ? g.Le2 : g.Le3;
+  int v = x[mu] + dir;
+  if (v < 0 || v >= Le) {
+    v = v < 0 ? v + Le : v - Le;
+    if (mu >= 2 && mu <= g.cstar) x[1] = geo_mirror_x1(g, x[1]);
+  }
+  x[mu] = v;
 }
-extern "C" qxd_status qxd_nn_harvest(qxd_handle*, const void*, int, void*, void*, int*, void*) { return QXD_EINVAL; }
-extern "C" qxd_status qxd_nn_train(qxd_handle*, qxd_nn*, const qxd_train_params*, const void*, const void*, int,
-                                   qxd_train_stats*, void*) {
-  return QXD_EINVAL;
+
+__device__ inline int nn_index(const Geo& g, const int* x) {
+  int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+  return p * g.Ve + geo_half(g, x[0], x[1], x[2], x[3]);
+}
+
+__device__ inline void nn_coords(const Geo& g, int q, int* x) {
+  int p = q >= g.Ve ? 1 : 0;
+  geo_decode(g, p, q - p * g.Ve, x[0], x[1], x[2], x[3]);
+}
+
+__device__ inline bf16x8 ld8(const uint16_t* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+enum { EPI_RELU = 0, EPI_SPINOR = 1, EPI_MASK = 2 };
+
+// out sites q in [0, nout); in and W as described above.
+// EPI_RELU:   out_act[q][c] = bf16(max(acc, 0))
+// EPI_SPINOR: out_f (F32 even half field) channel c < 24 = acc * scale (scale = sqrt(scal[i_s]) or 1)
+// EPI_MASK:   out_act[q][c] = mask[q][c] > 0 ? bf16(acc) : 0
+// SPARSE_IN: the input vanishes on odd sites (layer 1): taps landing on odd
+// sites are skipped when the whole wave has one parity.
+template <int EPI, bool SPARSE_IN>
+__global__ __launch_bounds__(256) void k_conv(Geo g, const uint16_t* __restrict__ in, const uint16_t* __restrict__ W,
+                                              int nout, uint16_t* __restrict__ out_act, float* __restrict__ out_f,
+                                              const uint16_t* __restrict__ mask, const double* __restrict__ scal,
+                                              int i_s) {
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int qbase = (blockIdx.x * 4 + wave) * 64;
+  if (qbase >= nout) return;
+  const int lr = l & 15, kc = (l >> 4) * 8;
+  int xs[4][4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    int q = qbase + rb * 16 + lr;
+    if (q >= nout) q = nout - 1;  // rows past the end compute a copy, never stored
+    nn_coords(g, q, xs[rb]);
+  }
+  const bool uni = (qbase + 64 <= g.Ve) || (qbase >= g.Ve);
+  const int pw = qbase >= g.Ve ? 1 : 0;
+  f4v acc[4][2];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
+  int tap = 0;
+  for (int d0 = -1; d0 <= 1; ++d0) {
+    int y0[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      for (int i = 0; i < 4; ++i) y0[rb][i] = xs[rb][i];
+      if (d0) nn_step(g, y0[rb], 0, d0);
+    }
+    for (int d1 = -1; d1 <= 1; ++d1) {
+      int y1[4][4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        for (int i = 0; i < 4; ++i) y1[rb][i] = y0[rb][i];
+        if (d1) nn_step(g, y1[rb], 1, d1);
+      }
+      for (int d2 = -1; d2 <= 1; ++d2) {
+        int y2[4][4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          for (int i = 0; i < 4; ++i) y2[rb][i] = y1[rb][i];
+          if (d2) nn_step(g, y2[rb], 2, d2);
+        }
+        for (int d3 = -1; d3 <= 1; ++d3, ++tap) {
+          if (SPARSE_IN && uni) {
+            int dist = (d0 != 0) + (d1 != 0) + (d2 != 0) + (d3 != 0);
+            if (((pw + dist) & 1) != 0) continue;  // every neighbour is odd: zero input
+          }
+          const uint16_t* wt = W + tap * (NN_C * NN_C);
+          bf16x8 b0 = ld8(wt + lr * NN_C + kc);
+          bf16x8 b1 = ld8(wt + (16 + lr) * NN_C + kc);
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb) {
+            int y3[4];
+            for (int i = 0; i < 4; ++i) y3[i] = y2[rb][i];
+            if (d3) nn_step(g, y3, 3, d3);
+            int qn = nn_index(g, y3);
+            bf16x8 a = ld8(in + (size_t)qn * NN_C + kc);
+            acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc[rb][0], 0, 0, 0);
+            acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc[rb][1], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  float scale = 1.0f;
+  if (EPI == EPI_SPINOR && scal) scale = (float)sqrt(scal[i_s]);
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int q = qbase + rb * 16 + (l >> 4) * 4 + i;
+        int c = cb * 16 + lr;
+        if (q >= nout) continue;
+        float vv = acc[rb][cb][i];
+        if (EPI == EPI_RELU) {
+          out_act[(size_t)q * NN_C + c] = f2bf(fmaxf(vv, 0.f));
+        } else if (EPI == EPI_MASK) {
+          out_act[(size_t)q * NN_C + c] = mask[(size_t)q * NN_C + c] != 0 && bf2f(mask[(size_t)q * NN_C + c]) > 0.f
+                                              ? f2bf(vv)
+                                              : (uint16_t)0;
+        } else {
+          if (c < 24) out_f[((size_t)(c >> 2) * g.Ve + q) * 4 + (c & 3)] = vv * scale;
+        }
+      }
+}
+
+// layer-1 input: even sites carry r / |r| (channel 2c + 0/1 = Re/Im of
+// component c), odd sites and channels 24..31 are zero
+__global__ __launch_bounds__(256) void k_nn_embed(Geo g, const float4* __restrict__ r, const double* __restrict__ scal,
+                                                  int i_n2, uint16_t* __restrict__ a0) {
+  int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= 2 * g.Ve) return;
+  uint16_t v[NN_C];
+  for (int c = 0; c < NN_C; ++c) v[c] = 0;
+  if (q < g.Ve) {
+    float s = scal ? (float)(1.0 / sqrt(scal[i_n2])) : 1.0f;
+    for (int j = 0; j < 6; ++j) {
+      float4 x = r[(size_t)j * g.Ve + q];
+      v[4 * j] = f2bf(s * x.x);
+      v[4 * j + 1] = f2bf(s * x.y);
+      v[4 * j + 2] = f2bf(s * x.z);
+      v[4 * j + 3] = f2bf(s * x.w);
+    }
+  }
+  uint4* o = reinterpret_cast<uint4*>(a0 + (size_t)q * NN_C);
+  for (int k = 0; k < 4; ++k)
+    o[k] = make_uint4(v[8 * k] | (v[8 * k + 1] << 16), v[8 * k + 2] | (v[8 * k + 3] << 16),
+                      v[8 * k + 4] | (v[8 * k + 5] << 16), v[8 * k + 6] | (v[8 * k + 7] << 16));
+}
+
+// padded bf16 forward and adjoint weights from the FP32 master copy
+__global__ void k_nn_pack(const float* __restrict__ w, uint16_t* __restrict__ wf, uint16_t* __restrict__ wa) {
+  int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= 3 * NN_LAYER_W) return;
+  int layer = t / NN_LAYER_W, r = t % NN_LAYER_W;
+  int tap = r / (NN_C * NN_C), co = (r / NN_C) % NN_C, ci = r % NN_C;
+  const int cin = layer == 0 ? 24 : 32, cout = layer == 2 ? 24 : 32;
+  const int off = layer == 0 ? 0 : layer == 1 ? 81 * 32 * 24 : 81 * 32 * 24 + 81 * 32 * 32;
+  float val = (co < cout && ci < cin) ? w[off + (tap * cout + co) * cin + ci] : 0.f;
+  uint16_t b = f2bf(val);
+  wf[t] = b;
+  // adjoint: reversed tap, transposed channels
+  wa[layer * NN_LAYER_W + ((80 - tap) * NN_C + ci) * NN_C + co] = b;
+}
+
+// loss of one pair and the gradient at the network output (even sites):
+// d = y - e / |r|;  g = 2 d |r|^2 / (|e|^2 B);  partial sum of |d|^2
+__global__ __launch_bounds__(256) void k_nn_lossgrad(Geo g, const float4* __restrict__ y, const float4* __restrict__ e,
+                                                     const double* __restrict__ scal, int i_r2, int i_e2, double invB,
+                                                     uint16_t* __restrict__ g3, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  int q = blockIdx.x * 256 + threadIdx.x;
+  double a = 0.0;
+  if (q < g.Ve) {
+    double r2 = scal[i_r2], e2 = scal[i_e2];
+    float ir = (float)(1.0 / sqrt(r2));
+    float f = (float)(2.0 * r2 / e2 * invB);
+    uint16_t v[NN_C];
+    for (int c = 0; c < NN_C; ++c) v[c] = 0;
+    for (int j = 0; j < 6; ++j) {
+      float4 yy = y[(size_t)j * g.Ve + q], ee = e[(size_t)j * g.Ve + q];
+      float d[4] = {yy.x - ir * ee.x, yy.y - ir * ee.y, yy.z - ir * ee.z, yy.w - ir * ee.w};
+      for (int k = 0; k < 4; ++k) {
+        a += (double)d[k] * (double)d[k];
+        v[4 * j + k] = f2bf(f * d[k]);
+      }
+    }
+    uint4* o = reinterpret_cast<uint4*>(g3 + (size_t)q * NN_C);
+    for (int k = 0; k < 4; ++k)
+      o[k] = make_uint4(v[8 * k] | (v[8 * k + 1] << 16), v[8 * k + 2] | (v[8 * k + 3] << 16),
+                        v[8 * k + 4] | (v[8 * k + 5] << 16), v[8 * k + 6] | (v[8 * k + 7] << 16));
+  }
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// weight-gradient partials: part[chunk][tap][co][ci] = sum_{q in chunk} gq[q][co] in[q + d][ci]
+// block: 4 waves, wave w takes tap blockIdx.y * 4 + w; sites in tiles of 64 transposed through LDS
+__global__ __launch_bounds__(256) void k_conv_wgrad(Geo g, const uint16_t* __restrict__ gq,
+                                                    const uint16_t* __restrict__ in, int nq, int chunk,
+                                                    float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) uint16_t gT[NN_C][72];
+  __shared__ __attribute__((aligned(16))) uint16_t aT[4][NN_C][72];
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int tap = blockIdx.y * 4 + wave;
+  const bool tap_ok = tap < NN_TAPS;
+  const int d0 = tap / 27 - 1, d1 = (tap / 9) % 3 - 1, d2 = (tap / 3) % 3 - 1, d3 = tap % 3 - 1;
+  f16v acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  const int q_begin = blockIdx.x * chunk;
+  for (int q0 = q_begin; q0 < q_begin + chunk && q0 < nq; q0 += 64) {
+    __syncthreads();
+    {
+      int si = threadIdx.x >> 2, c8 = (threadIdx.x & 3) * 8;
+      int q = q0 + si;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (q < nq) v = *reinterpret_cast<const uint4*>(gq + (size_t)q * NN_C + c8);
+      uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+      for (int i = 0; i < 4; ++i) {
+        gT[c8 + 2 * i][si] = (uint16_t)(w4[i] & 0xffff);
+        gT[c8 + 2 * i + 1][si] = (uint16_t)(w4[i] >> 16);
+      }
+    }
+    if (tap_ok) {
+      int q = q0 + l;
+      bool ok = q < nq;
+      int x[4];
+      nn_coords(g, ok ? q : 0, x);
+      if (d0) nn_step(g, x, 0, d0);
+      if (d1) nn_step(g, x, 1, d1);
+      if (d2) nn_step(g, x, 2, d2);
+      if (d3) nn_step(g, x, 3, d3);
+      int qn = nn_index(g, x);
+      for (int c8 = 0; c8 < NN_C; c8 += 8) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (ok) v = *reinterpret_cast<const uint4*>(in + (size_t)qn * NN_C + c8);
+        uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+        for (int i = 0; i < 4; ++i) {
+          aT[wave][c8 + 2 * i][l] = (uint16_t)(w4[i] & 0xffff);
+          aT[wave][c8 + 2 * i + 1][l] = (uint16_t)(w4[i] >> 16);
+        }
+      }
+    }
+    __syncthreads();
+    if (tap_ok) {
+#pragma unroll
+      for (int k0 = 0; k0 < 64; k0 += 16) {
+        int kk = k0 + (l >> 5) * 8;
+        bf16x8 a = *reinterpret_cast<const bf16x8*>(&gT[l & 31][kk]);
+        bf16x8 b = *reinterpret_cast<const bf16x8*>(&aT[wave][l & 31][kk]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+    }
+  }
+  if (tap_ok) {
+    float* o = part + ((size_t)blockIdx.x * NN_TAPS + tap) * (NN_C * NN_C);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int row = (i / 4) * 8 + (l >> 5) * 4 + (i & 3);
+      o[row * NN_C + (l & 31)] = acc[i];
+    }
+  }
+}
+
+// grad[off + (tap cout + co) cin + ci] += sum over chunks (fixed order)
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunk, int cin, int cout, int off,
+                               float* __restrict__ grad) {
+  int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= NN_TAPS * cout * cin) return;
+  int tap = t / (cout * cin), co = (t / cin) % cout, ci = t % cin;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[((size_t)c * NN_TAPS + tap) * (NN_C * NN_C) + co * NN_C + ci];
+  grad[off + t] += (float)s;
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float gi = g[i];
+  float mi = b1 * m[i] + (1.f - b1) * gi;
+  float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static qxd_status nn_repack(qxd_nn* net, hipStream_t s) {
+  hipLaunchKernelGGL(k_nn_pack, dim3(div_up(3 * NN_LAYER_W, 256)), dim3(256), 0, s, net->w, net->wf, net->wa);
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}
+
+static void conv_launch(qxd_handle* h, int layer, const uint16_t* in, const uint16_t* W, int nout, int epi,
+                        uint16_t* out_act, float* out_f, const uint16_t* mask, const double* scal, int i_s,
+                        hipStream_t s) {
+  int waves = div_up(nout, 64);
+  dim3 grid(div_up(waves, 4));
+  const uint16_t* wl = W + (size_t)layer * NN_LAYER_W;
+  if (epi == EPI_RELU) {
+    if (layer == 0)
+      hipLaunchKernelGGL((k_conv<EPI_RELU, true>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
+                         scal, i_s);
+    else
+      hipLaunchKernelGGL((k_conv<EPI_RELU, false>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
+                         scal, i_s);
+  } else if (epi == EPI_SPINOR) {
+    hipLaunchKernelGGL((k_conv<EPI_SPINOR, false>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
+                       scal, i_s);
+  } else {
+    hipLaunchKernelGGL((k_conv<EPI_MASK, false>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
+                       scal, i_s);
+  }
+}
+
+static qxd_status nn_alloc_act(qxd_nn* net) {
+  if (net->a0) return QXD_OK;
+  size_t bytes = (size_t)net->h->V * NN_C * sizeof(uint16_t);
+  if (hipMalloc(&net->a0, bytes) != hipSuccess || hipMalloc(&net->a1, bytes) != hipSuccess ||
+      hipMalloc(&net->a2, bytes) != hipSuccess)
+    return QXD_ENOMEM;
+  return QXD_OK;
+}
+
+static qxd_status nn_alloc_train(qxd_nn* net, hipStream_t s) {
+  QXD_TRY(nn_alloc_act(net));
+  if (net->g3) return QXD_OK;
+  qxd_handle* h = net->h;
+  size_t bytes = (size_t)h->V * NN_C * sizeof(uint16_t);
+  net->nchunk = div_up(h->V, kWgChunk);
+  if (hipMalloc(&net->g3, bytes) != hipSuccess || hipMalloc(&net->gA, bytes) != hipSuccess ||
+      hipMalloc(&net->gB, bytes) != hipSuccess ||
+      hipMalloc(&net->y, (size_t)h->Ve * 24 * sizeof(float)) != hipSuccess ||
+      hipMalloc(&net->part, (size_t)net->nchunk * NN_TAPS * NN_C * NN_C * sizeof(float)) != hipSuccess)
+    return QXD_ENOMEM;
+  // the odd half of g3 is never written: zero once
+  QXD_HIP(hipMemsetAsync(net->g3, 0, bytes, s));
+  return QXD_OK;
+}
+
+// forward pass on r (F32 even half): activations a0, a1, a2 and output
+// out = scale * N(r / |r|) (scale = |r| when with_norm, else 1 and no input scaling)
+static qxd_status nn_forward(qxd_handle* h, qxd_nn* net, const float4* r, float* out, bool with_norm, hipStream_t s) {
+  QXD_TRY(nn_alloc_act(net));
+  if (with_norm) blas_norm2<float4>(h, r, (size_t)6 * h->Ve, h->scal + S_NN, s);
+  hipLaunchKernelGGL(k_nn_embed, dim3(div_up(2 * h->Ve, 256)), dim3(256), 0, s, h->geo, r,
+                     with_norm ? h->scal : nullptr, S_NN, net->a0);
+  conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s);
+  conv_launch(h, 1, net->a1, net->wf, (int)h->V, EPI_RELU, net->a2, nullptr, nullptr, nullptr, 0, s);
+  conv_launch(h, 2, net->a2, net->wf, (int)h->Ve, EPI_SPINOR, nullptr, out, nullptr, with_norm ? h->scal : nullptr,
+              S_NN, s);
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}
+
+qxd_status nn_apply_internal(qxd_handle* h, qxd_nn* net, float4* out_e, const float4* in_e, hipStream_t s) {
+  if (!net || net->h != h) return QXD_EINVAL;
+  return nn_forward(h, net, in_e, reinterpret_cast<float*>(out_e), true, s);
+}
+
+// loss of one pair (r, e) and, with `backward`, accumulation of its weight
+// gradient (scaled by invB) into net->grad.  Device scalars: slot + 0 = |r|^2,
+// slot + 1 = |e|^2, slot + 2 = |N(rhat) - ehat|^2 |e|^2 / |r|^2... stored raw as
+// |N(rhat) - e/|r||^2; the pair loss is scal[slot+2] scal[slot] / scal[slot+1].
+static qxd_status nn_pair(qxd_handle* h, qxd_nn* net, const float4* r, const float4* e, double invB, int slot,
+                          bool backward, hipStream_t s) {
+  size_t nw = (size_t)6 * h->Ve;
+  blas_norm2<float4>(h, r, nw, h->scal + slot, s);
+  blas_norm2<float4>(h, e, nw, h->scal + slot + 1, s);
+  // forward on r / |r| (scale 1 at the output): y = N(rhat)
+  hipLaunchKernelGGL(k_nn_embed, dim3(div_up(2 * h->Ve, 256)), dim3(256), 0, s, h->geo, r, h->scal, slot, net->a0);
+  conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s);
+  conv_launch(h, 1, net->a1, net->wf, (int)h->V, EPI_RELU, net->a2, nullptr, nullptr, nullptr, 0, s);
+  conv_launch(h, 2, net->a2, net->wf, (int)h->Ve, EPI_SPINOR, nullptr, net->y, nullptr, nullptr, 0, s);
+  // output gradient and loss partials
+  int G = div_up(h->Ve, 256);
+  hipLaunchKernelGGL(k_nn_lossgrad, dim3(G), dim3(256), 0, s, h->geo, (const float4*)net->y, e, h->scal, slot,
+                     slot + 1, invB, net->g3, h->partial);
+  launch_final_sum(h->partial, G, 1, G, h->scal + slot + 2, s);
+  if (!backward) return QXD_OK;
+  // layer 3: weight gradient over the even sites, data gradient masked by a2 > 0
+  dim3 wg(net->nchunk, div_up(NN_TAPS, 4));
+  dim3 wg_e(div_up(h->Ve, kWgChunk), div_up(NN_TAPS, 4));
+  hipLaunchKernelGGL(k_conv_wgrad, wg_e, dim3(256), 0, s, h->geo, net->g3, net->a2, (int)h->Ve, kWgChunk, net->part);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(div_up(NN_TAPS * 24 * 32, 256)), dim3(256), 0, s, net->part,
+                     (int)wg_e.x, 32, 24, kOff[2], net->grad);
+  conv_launch(h, 2, net->g3, net->wa, (int)h->V, EPI_MASK, net->gA, nullptr, net->a2, nullptr, 0, s);
+  // layer 2
+  hipLaunchKernelGGL(k_conv_wgrad, wg, dim3(256), 0, s, h->geo, net->gA, net->a1, (int)h->V, kWgChunk, net->part);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(div_up(NN_TAPS * 32 * 32, 256)), dim3(256), 0, s, net->part, net->nchunk,
+                     32, 32, kOff[1], net->grad);
+  conv_launch(h, 1, net->gA, net->wa, (int)h->V, EPI_MASK, net->gB, nullptr, net->a1, nullptr, 0, s);
+  // layer 1
+  hipLaunchKernelGGL(k_conv_wgrad, wg, dim3(256), 0, s, h->geo, net->gB, net->a0, (int)h->V, kWgChunk, net->part);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(div_up(NN_TAPS * 32 * 24, 256)), dim3(256), 0, s, net->part, net->nchunk,
+                     24, 32, kOff[0], net->grad);
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
+}
+
+static double pair_loss(const qxd_handle* h, int slot) {
+  return h->scal_host[slot + 2] * h->scal_host[slot] / h->scal_host[slot + 1];
+}
+
+extern "C" qxd_status qxd_nn_create(qxd_handle* h, qxd_nn** out) {
+  if (!h || !out) return QXD_EINVAL;
+  qxd_nn* net = new (std::nothrow) qxd_nn();
+  if (!net) return QXD_ENOMEM;
+  net->h = h;
+  size_t n = QXD_NN_NWEIGHTS;
+  if (hipMalloc(&net->w, n * 4) != hipSuccess || hipMalloc(&net->m, n * 4) != hipSuccess ||
+      hipMalloc(&net->v, n * 4) != hipSuccess || hipMalloc(&net->grad, n * 4) != hipSuccess ||
+      hipMalloc(&net->wf, (size_t)3 * NN_LAYER_W * 2) != hipSuccess ||
+      hipMalloc(&net->wa, (size_t)3 * NN_LAYER_W * 2) != hipSuccess) {
+    qxd_nn_destroy(net);
+    return QXD_ENOMEM;
+  }
+  if (hipMemset(net->w, 0, n * 4) != hipSuccess || hipMemset(net->m, 0, n * 4) != hipSuccess ||
+      hipMemset(net->v, 0, n * 4) != hipSuccess || hipMemset(net->grad, 0, n * 4) != hipSuccess) {
+    qxd_nn_destroy(net);
+    return QXD_EHIP;
+  }
+  if (nn_repack(net, nullptr) != QXD_OK || hipDeviceSynchronize() != hipSuccess) {
+    qxd_nn_destroy(net);
+    return QXD_EHIP;
+  }
+  *out = net;
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_nn_destroy(qxd_nn* net) {
+  if (!net) return QXD_EINVAL;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {net->w, net->wf, net->wa, net->m, net->v, net->grad, net->a0, net->a1,
+                  net->a2, net->g3, net->gA, net->gB, net->y, net->part};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete net;
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_nn_set_weights(qxd_nn* net, const float* w) {
+  if (!net || !w) return QXD_EINVAL;
+  // non-finite weights are accepted: the solver detects and drops the
+  // directions such a network produces
+  QXD_HIP(hipMemcpy(net->w, w, QXD_NN_NWEIGHTS * sizeof(float), hipMemcpyHostToDevice));
+  QXD_HIP(hipMemset(net->m, 0, QXD_NN_NWEIGHTS * 4));
+  QXD_HIP(hipMemset(net->v, 0, QXD_NN_NWEIGHTS * 4));
+  net->t = 0;
+  QXD_TRY(nn_repack(net, nullptr));
+  QXD_HIP(hipDeviceSynchronize());
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_nn_get_weights(qxd_nn* net, float* w) {
+  if (!net || !w) return QXD_EINVAL;
+  QXD_HIP(hipDeviceSynchronize());
+  QXD_HIP(hipMemcpy(w, net->w, QXD_NN_NWEIGHTS * sizeof(float), hipMemcpyDeviceToHost));
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_nn_apply(qxd_handle* h, qxd_nn* net, void* out_e, const void* in_e, void* stream) {
+  if (!h || !net || !out_e || !in_e || out_e == in_e) return QXD_EINVAL;
+  return nn_apply_internal(h, net, (float4*)out_e, (const float4*)in_e, as_stream(stream));
+}
+
+extern "C" qxd_status qxd_nn_loss_grad(qxd_handle* h, qxd_nn* net, const void* r, const void* e, int n, double* loss,
+                                       float* grad, void* stream) {
+  if (!h || !net || !r || !e || n < 1 || net->h != h) return QXD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  QXD_TRY(nn_alloc_train(net, s));
+  QXD_HIP(hipMemsetAsync(net->grad, 0, QXD_NN_NWEIGHTS * 4, s));
+  size_t half = (size_t)6 * h->Ve;
+  double total = 0.0;
+  for (int i = 0; i < n; ++i) {
+    QXD_TRY(nn_pair(h, net, (const float4*)r + i * half, (const float4*)e + i * half, 1.0 / n, S_NN, true, s));
+    QXD_HIP(hipMemcpyAsync(h->scal_host + S_NN, h->scal + S_NN, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    QXD_HIP(hipStreamSynchronize(s));
+    total += pair_loss(h, S_NN) / n;
+  }
+  if (loss) *loss = total;
+  if (grad) {
+    QXD_HIP(hipMemcpyAsync(grad, net->grad, QXD_NN_NWEIGHTS * 4, hipMemcpyDeviceToHost, s));
+    QXD_HIP(hipStreamSynchronize(s));
+  }
+  return QXD_OK;
+}
+
+static uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Adam on minibatches of pairs; the last p->holdout pairs are only evaluated.
+extern "C" qxd_status qxd_nn_train(qxd_handle* h, qxd_nn* net, const qxd_train_params* p, const void* r, const void* e,
+                                   int npairs, qxd_train_stats* stats, void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!h || !net || !p || !r || !e || net->h != h) return QXD_EINVAL;
+  int ntrain = npairs - std::max(0, p->holdout);
+  if (ntrain < 1 || p->batch < 1 || p->batch > 64 || p->epochs < 1) return QXD_EINVAL;
+  hipStream_t s = as_stream(stream);
+  QXD_TRY(nn_alloc_train(net, s));
+  size_t half = (size_t)6 * h->Ve;
+  const float4* R = (const float4*)r;
+  const float4* E = (const float4*)e;
+  std::vector<int> order(ntrain);
+  for (int i = 0; i < ntrain; ++i) order[i] = i;
+  uint64_t seed = p->seed;
+  qxd_train_stats st{};
+  const int base = S_NN + 8;
+  for (int ep = 0; ep < p->epochs; ++ep) {
+    for (int i = ntrain - 1; i > 0; --i) std::swap(order[i], order[(int)(splitmix64(seed) % (uint64_t)(i + 1))]);
+    double ep_loss = 0.0;
+    for (int b0 = 0; b0 < ntrain; b0 += p->batch) {
+      int nb = std::min(p->batch, ntrain - b0);
+      QXD_HIP(hipMemsetAsync(net->grad, 0, QXD_NN_NWEIGHTS * 4, s));
+      for (int k = 0; k < nb; ++k) {
+        int idx = order[b0 + k];
+        QXD_TRY(nn_pair(h, net, R + idx * half, E + idx * half, 1.0 / nb, base + 3 * k, true, s));
+      }
+      net->t++;
+      float c1 = 1.f - (float)std::pow(p->beta1, (double)net->t), c2 = 1.f - (float)std::pow(p->beta2, (double)net->t);
+      hipLaunchKernelGGL(k_adam, dim3(div_up(QXD_NN_NWEIGHTS, 256)), dim3(256), 0, s, net->w, net->grad, net->m,
+                         net->v, (int)QXD_NN_NWEIGHTS, (float)p->lr, (float)p->beta1, (float)p->beta2, (float)p->eps,
+                         c1, c2);
+      QXD_TRY(nn_repack(net, s));
+      QXD_HIP(hipMemcpyAsync(h->scal_host + base, h->scal + base, 3 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      QXD_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k < nb; ++k) ep_loss += pair_loss(h, base + 3 * k);
+      st.steps++;
+    }
+    ep_loss /= ntrain;
+    if (!std::isfinite(ep_loss)) return QXD_ENAN;
+    if (ep == 0) st.loss_first = ep_loss;
+    st.loss_last = ep_loss;
+  }
+  double hl = 0.0;
+  int nh = npairs - ntrain;
+  for (int i = 0; i < nh; ++i) {
+    QXD_TRY(nn_pair(h, net, R + (ntrain + i) * half, E + (ntrain + i) * half, 1.0, base, false, s));
+    QXD_HIP(hipMemcpyAsync(h->scal_host + base, h->scal + base, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    QXD_HIP(hipStreamSynchronize(s));
+    hl += pair_loss(h, base) / nh;
+  }
+  st.holdout_loss = nh > 0 ? hl : 0.0;
+  st.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = st;
+  return QXD_OK;
 }

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <functional>
 #include <vector>
 
 #include "blas.hpp"
@@ -88,7 +89,8 @@ struct FgcrResult {
 // each cycle x += Phi alpha with R alpha = c solved on the host in FP64.
 template <class VT>
 qxd_status fgcr(qxd_handle* h, InnerOp op, qxd_nn* net, int fallback_after, VT* x, VT* r, size_t n, int nkv,
-                double tol_abs, int max_steps, FgcrResult* res, hipStream_t s) {
+                double tol_abs, int max_steps, FgcrResult* res, hipStream_t s,
+                const std::function<qxd_status()>* on_cycle = nullptr) {
   std::vector<VT*> phi(nkv), chi(nkv);
   size_t bytes = n * sizeof(VT);
   for (int k = 0; k < nkv; ++k) {
@@ -179,6 +181,7 @@ qxd_status fgcr(qxd_handle* h, InnerOp op, qxd_nn* net, int fallback_after, VT* 
     Ptrs pp{};
     for (int j = 0; j < m; ++j) pp.p[j] = phi[j];
     blas_multi_axpy<VT>(h, x, pp, m, h->scal + S_FAL, n, s);
+    if (on_cycle) QXD_TRY((*on_cycle)());
   }
   res->steps = steps;
   res->rr = rr;
@@ -354,5 +357,93 @@ extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm
   st.status = rc;
   st.t_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
   if (stats) *stats = st;
+  return rc;
+}
+
+// Training pairs from the method's own solves: plain FP64 GCR (restart 4, no
+// preconditioner) on D_hat x = bhat, with the iterate x_k and the recursive
+// residual r_k recorded at restarts; after convergence e_k = x* - x_k (formed
+// in FP64), so that D_hat e_k = r_k up to the final residual.  npairs snapshots
+// evenly spread over the recorded part of the solve are returned as FP32 even
+// half fields.
+extern "C" qxd_status qxd_nn_harvest(qxd_handle* h, const void* b, int npairs, void* r_out, void* e_out,
+                                     int* n_harvested, void* stream) {
+  if (!h || !b || npairs < 1 || !r_out || !e_out) return QXD_EINVAL;
+  if (!h->has_inverse) return QXD_ESTATE;
+  hipStream_t s = as_stream(stream);
+  size_t n64 = (size_t)12 * h->Ve, b64 = n64 * sizeof(double2);
+  double2 *bh = (double2*)ws_get(h, W_BH, b64), *xe = (double2*)ws_get(h, W_XE, b64);
+  double2 *r = (double2*)ws_get(h, W_R, b64), *w = (double2*)ws_get(h, W_W, b64);
+  if (!bh || !xe || !r || !w) return QXD_ENOMEM;
+  double nb;
+  QXD_TRY(norm_full(h, (const double2*)b, &nb, s));
+  QXD_TRY(qxd_eo_source(h, bh, b, s));
+  QXD_HIP(hipMemcpyAsync(r, bh, b64, hipMemcpyDeviceToDevice, s));
+  // snapshots (x_k, r_k) at every `stride`-th restart; when more than `cap` are
+  // held, every other one is dropped and the stride doubles, so at most cap
+  // snapshots, evenly spread over the solve, are kept
+  std::vector<double2*> snaps;
+  const int cap = 2 * npairs + 2;
+  int64_t cycle = 0, stride = 1;
+  qxd_status cb_status = QXD_OK;
+  // pairs are recorded while |r_k| > 1e-6 |bhat|: e_k = x* - x_k solves
+  // D_hat e_k = r_k - r*, with |r*| <= 1e-10 |b|, so later pairs would carry a
+  // relative error above 1e-4
+  blas_norm2<double2>(h, bh, n64, h->scal + S_BH, s);
+  QXD_TRY(read_scal(h, S_BH, 1, s));
+  const double rec_floor = 1e-6 * std::sqrt(h->scal_host[S_BH]);
+  std::function<qxd_status()> on_cycle = [&]() -> qxd_status {
+    if (std::sqrt(h->scal_host[S_FRR]) < rec_floor) return QXD_OK;
+    if (cycle++ % stride != 0) return QXD_OK;
+    double2 *xs = nullptr, *rs = nullptr;
+    if (hipMalloc(&xs, b64) != hipSuccess || hipMalloc(&rs, b64) != hipSuccess) {
+      if (xs) (void)hipFree(xs);
+      cb_status = QXD_ENOMEM;
+      return QXD_ENOMEM;
+    }
+    QXD_HIP(hipMemcpyAsync(xs, xe, b64, hipMemcpyDeviceToDevice, s));
+    QXD_HIP(hipMemcpyAsync(rs, r, b64, hipMemcpyDeviceToDevice, s));
+    snaps.push_back(xs);
+    snaps.push_back(rs);
+    if ((int)snaps.size() / 2 > cap) {
+      QXD_HIP(hipStreamSynchronize(s));
+      std::vector<double2*> keep;
+      for (size_t k = 0; k < snaps.size() / 2; ++k) {
+        if (k % 2 == 0) {
+          keep.push_back(snaps[2 * k]);
+          keep.push_back(snaps[2 * k + 1]);
+        } else {
+          (void)hipFree(snaps[2 * k]);
+          (void)hipFree(snaps[2 * k + 1]);
+        }
+      }
+      snaps.swap(keep);
+      stride *= 2;
+    }
+    return QXD_OK;
+  };
+  FgcrResult fr;
+  InnerOp op{0};
+  qxd_status rc = fgcr<double2>(h, op, nullptr, 1 << 30, xe, r, n64, 4, 1e-10 * nb, 50000, &fr, s, &on_cycle);
+  int nsnap = (int)snaps.size() / 2;
+  if (rc == QXD_OK && nsnap > 0) {
+    int take = std::min(npairs, nsnap);
+    h->scal_host[S_ONE] = 1.0;
+    QXD_HIP(hipMemcpyAsync(h->scal + S_ONE, h->scal_host + S_ONE, sizeof(double), hipMemcpyHostToDevice, s));
+    size_t half32 = (size_t)6 * h->Ve;
+    for (int i = 0; i < take; ++i) {
+      int k = take == 1 ? nsnap - 1 : (int)((int64_t)i * (nsnap - 1) / (take - 1));
+      blas_sub_norm<double2>(h, w, xe, snaps[2 * k], n64, h->scal + S_RT, s);  // e_k = x* - x_k
+      blas_down(h, (float4*)e_out + i * half32, w, S_ONE, s);
+      blas_down(h, (float4*)r_out + i * half32, snaps[2 * k + 1], S_ONE, s);
+    }
+    QXD_HIP(hipStreamSynchronize(s));
+    if (n_harvested) *n_harvested = take;
+  } else if (n_harvested) {
+    *n_harvested = 0;
+  }
+  QXD_HIP(hipStreamSynchronize(s));
+  for (double2* p : snaps) (void)hipFree(p);
+  if (cb_status != QXD_OK) return cb_status;
   return rc;
 }

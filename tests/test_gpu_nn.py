@@ -1,0 +1,209 @@
+"""Learned preconditioner on the GPU, through the C ABI.
+
+Forward and weight gradients are compared with the FP64 network oracle run on
+the same weights rounded to bfloat16 (the GPU contracts bf16 operands on the
+matrix cores and stores bf16 activations, so a few 1e-3 of relative noise per
+layer remain: the bars are 2e-2 for outputs and losses, 6e-2 for gradients, in
+norm).  Training, the preconditioned solve and the fallbacks are checked on the
+FP64 true residual."""
+import numpy as np
+import pytest
+
+import oracle
+import synthgen as sg
+from oracle import nn as onn
+from tests.gpu_common import make_pair, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+qxd = pytest.importorskip("paper_1908_11673_amd")
+
+FD = sg.FLAVOURS["d"]
+SHAPES = [(24, 32), (32, 32), (32, 24)]
+
+
+def init_weights(seed, scale=1.0):
+    ws = []
+    for k, (ci, co) in enumerate(SHAPES):
+        ws.append(sg.gaussian(seed, k, scale * np.sqrt(2.0 / (81 * ci)), 81 * co * ci).reshape(81, co, ci))
+    return ws
+
+
+def flat(ws):
+    return np.concatenate([w.reshape(-1) for w in ws]).astype(np.float32)
+
+
+def bf16_round(a):
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def half32(lat, o, psi):
+    """even-site spinor -> FP32 even half field on the device"""
+    return lat.pack(to_dev(psi), qxd.F32)[:12 * lat.Ve].clone()
+
+
+def from_half32(lat, o, t):
+    full = lat.field(qxd.F32, full=True)
+    full[:12 * lat.Ve] = t
+    return lat.unpack(full, qxd.F32).cpu().numpy()
+
+
+@pytest.fixture(scope="module", params=[((4, 2, 4, 4), 3), ((2, 4, 2, 6), 2), ((8, 4, 4, 4), 1)],
+                ids=["cs3", "cs2_ragged", "c0"])
+def lat_pair(request):
+    L, cstar = request.param
+    o, lat, _ = make_pair(L, cstar, FD, sigma=0.2, su1=0.3, seed=31)
+    yield o, lat
+    lat.close()
+
+
+def test_forward_matches_oracle(lat_pair):
+    o, lat = lat_pair
+    ws = init_weights(5)
+    net = qxd.qxd_nn_create(lat.h)
+    qxd.qxd_nn_set_weights(net, flat(ws))
+    r = sg.spinor(41, o.V)
+    r[o.parity() == 1] = 0
+    out = lat.field(qxd.F32)
+    qxd.qxd_nn_apply(lat.h, net, out, half32(lat, o, r))
+    got = from_half32(lat, o, out)
+    want = onn.apply_precond(o, [bf16_round(w) for w in ws], r)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print("nn forward rel err %.2e" % err)
+    assert err < 2e-2
+    assert np.abs(got[o.parity() == 1]).max() == 0
+    # positive homogeneity: M(2 r) = 2 M(r) exactly
+    out2 = lat.field(qxd.F32)
+    qxd.qxd_nn_apply(lat.h, net, out2, half32(lat, o, 2 * r))
+    assert torch.equal(out2, 2 * out)
+    qxd.qxd_nn_destroy(net)
+
+
+def test_loss_and_gradient_match_oracle(lat_pair):
+    o, lat = lat_pair
+    ws = init_weights(6, scale=1.5)
+    net = qxd.qxd_nn_create(lat.h)
+    qxd.qxd_nn_set_weights(net, flat(ws))
+    par = o.parity()
+    rs, es = [], []
+    for k in range(2):
+        r = sg.spinor(50 + k, o.V)
+        e = sg.spinor(60 + k, o.V)
+        r[par == 1] = 0
+        e[par == 1] = 0
+        rs.append(r)
+        es.append(e)
+    R = torch.cat([half32(lat, o, r) for r in rs])
+    E = torch.cat([half32(lat, o, e) for e in es])
+    loss, grad = qxd.qxd_nn_loss_grad(lat.h, net, R, E, 2)
+    wr = [bf16_round(w) for w in ws]
+    L0, g0 = onn.loss_and_grad(o, wr, rs, es)
+    print("loss gpu %.6f oracle %.6f" % (loss, L0))
+    assert abs(loss - L0) / L0 < 2e-2
+    off = 0
+    for k, (ci, co) in enumerate(SHAPES):
+        n = 81 * co * ci
+        gk = grad[off:off + n].reshape(81, co, ci)
+        off += n
+        err = np.linalg.norm(gk - g0[k]) / np.linalg.norm(g0[k])
+        print("layer %d grad rel err %.2e" % (k + 1, err))
+        assert err < 6e-2
+    qxd.qxd_nn_destroy(net)
+
+
+def test_zero_weights_fall_back_and_still_converge(lat_pair):
+    o, lat = lat_pair
+    net = qxd.qxd_nn_create(lat.h)
+    qxd.qxd_nn_set_weights(net, np.zeros(qxd.NN_NWEIGHTS, np.float32))
+    b = sg.spinor(70, o.V)
+    x = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32), net, x, lat.pack(to_dev(b)))
+    assert st["fell_back"] == 1 and st["true_residual"] <= 1e-10
+    res = np.linalg.norm(b - o.dirac(lat.unpack(x).cpu().numpy())) / np.linalg.norm(b)
+    assert res <= 1e-10
+    qxd.qxd_nn_destroy(net)
+
+
+def test_nan_weights_fall_back_and_still_converge(lat_pair):
+    o, lat = lat_pair
+    net = qxd.qxd_nn_create(lat.h)
+    w = flat(init_weights(7))
+    w[100] = np.nan
+    qxd.qxd_nn_set_weights(net, w)
+    b = sg.spinor(71, o.V)
+    x = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32), net, x, lat.pack(to_dev(b)))
+    assert st["fell_back"] == 1 and st["true_residual"] <= 1e-10
+    qxd.qxd_nn_destroy(net)
+
+
+def test_harvest_pairs_satisfy_the_schur_equation(lat_pair):
+    o, lat = lat_pair
+    b = sg.spinor(72, o.V)
+    n = 6
+    R = torch.zeros(n * 12 * lat.Ve, dtype=torch.complex64, device="cuda")
+    E = torch.zeros_like(R)
+    got = qxd.qxd_nn_harvest(lat.h, lat.pack(to_dev(b)), n, R, E)
+    assert got >= 2
+    nbh = np.linalg.norm(o.eo_source(b))
+    for i in range(got):
+        r = from_half32(lat, o, R[i * 12 * lat.Ve:(i + 1) * 12 * lat.Ve])
+        e = from_half32(lat, o, E[i * 12 * lat.Ve:(i + 1) * 12 * lat.Ve])
+        # D_hat e_k = r_k - r_final: pairs are taken while |r_k| > 1e-6 |bhat|, the
+        # final residual is below 1e-10 |b|, and both fields are rounded to FP32
+        assert np.linalg.norm(r) >= 0.99e-6 * nbh
+        err = np.linalg.norm(o.schur(e) - r) / np.linalg.norm(r)
+        assert err < 2e-4, (i, err)
+
+
+def test_training_lowers_the_loss_and_the_solve_stays_exact():
+    """Train on pairs harvested from a few small fields; the network-preconditioned
+    solve of a held-out field must still reach the FP64 true residual (whether the
+    network helps at this toy scale is reported, not asserted)."""
+    L, cstar = (8, 4, 4, 4), 3
+    flav = FD
+    lat = qxd.Lattice(L, cstar)
+    Vp = int(np.prod(L))
+    pairs_r, pairs_e = [], []
+    npf = 12
+    for seed in range(3):
+        U = sg.gauge_su3(300 + seed, 0.2, Vp)
+        A = sg.gauge_u1(300 + seed, 0.3, Vp)
+        lat.setup(U, A, flav)
+        for src in range(2):
+            b = sg.spinor(400 + 10 * seed + src, lat.V)
+            R = torch.zeros(npf * 12 * lat.Ve, dtype=torch.complex64, device="cuda")
+            E = torch.zeros_like(R)
+            got = qxd.qxd_nn_harvest(lat.h, lat.pack(to_dev(b)), npf, R, E)
+            pairs_r.append(R[:got * 12 * lat.Ve])
+            pairs_e.append(E[:got * 12 * lat.Ve])
+    R = torch.cat(pairs_r)
+    E = torch.cat(pairs_e)
+    npairs = R.numel() // (12 * lat.Ve)
+    net = qxd.qxd_nn_create(lat.h)
+    qxd.qxd_nn_set_weights(net, flat(init_weights(9, scale=0.5)))
+    st = qxd.qxd_nn_train(lat.h, net, qxd.train_params(epochs=30, batch=8, lr=2e-3, holdout=8), R, E, npairs)
+    print("training", st)
+    assert st["loss_last"] < 0.7 * st["loss_first"]
+    U = sg.gauge_su3(399, 0.2, Vp)
+    A = sg.gauge_u1(399, 0.3, Vp)
+    lat.setup(U, A, flav)
+    o = oracle.Oracle(L, cstar)
+    o.set_gauge_physical(U, A)
+    o.set_flavour(**flav)
+    b = sg.spinor(499, lat.V)
+    bd = lat.pack(to_dev(b))
+    x = lat.field(qxd.F64, full=True)
+    plain = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32, nkv=16), None, x, bd)
+    x2 = lat.field(qxd.F64, full=True)
+    learned = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32, nkv=16), net, x2, bd)
+    print("plain FGCR", plain)
+    print("NN FGCR", learned)
+    assert learned["true_residual"] <= 1e-10
+    res = np.linalg.norm(b - o.dirac(lat.unpack(x2).cpu().numpy())) / np.linalg.norm(b)
+    assert res <= 1e-10
+    qxd.qxd_nn_destroy(net)
+    lat.close()
