@@ -209,6 +209,10 @@ typedef struct {
   double beta1, beta2, eps;
   int holdout;         /* the last `holdout` pairs are not trained on */
   uint64_t seed;       /* shuffling order */
+  int loss;            /* 0: |N(rhat) - ehat|^2 / |ehat|^2;
+                          1: |D_hat (N(rhat) - ehat)|^2 / |rhat|^2 (rhat = D_hat ehat):
+                             the same error measured in the D_hat^+ D_hat norm, i.e.
+                             the residual left after one preconditioned step */
 } qxd_train_params;
 
 typedef struct {
@@ -221,6 +225,10 @@ typedef struct {
 
 qxd_status qxd_nn_create(qxd_handle *h, qxd_nn **net);
 qxd_status qxd_nn_destroy(qxd_nn *net);
+/* Linear skip: M(r) = |r| (N(r/|r|) + skip r/|r|) (default 0: the plain network).
+ * A bias-free ReLU network of these widths cannot represent a linear map of 24
+ * channels; with a skip it learns a correction to skip * identity. */
+qxd_status qxd_nn_set_skip(qxd_nn *net, double skip);
 /* Host pointers to QXD_NN_NWEIGHTS floats (synchronous). */
 qxd_status qxd_nn_set_weights(qxd_nn *net, const float *w);
 qxd_status qxd_nn_get_weights(qxd_nn *net, float *w);
@@ -229,9 +237,10 @@ qxd_status qxd_nn_get_weights(qxd_nn *net, float *w);
 qxd_status qxd_nn_apply(qxd_handle *h, qxd_nn *net, void *out_e, const void *in_e, void *stream);
 
 /* Loss and FP32 weight gradient (host, QXD_NN_NWEIGHTS floats) over a batch of
- * pairs: mean_i |N(r_i/|r_i|) - e_i/|r_i||^2 / |e_i/|r_i||^2.  r, e: device arrays
- * of n F32 even half fields, one after another.  Synchronous. */
-qxd_status qxd_nn_loss_grad(qxd_handle *h, qxd_nn *net, const void *r, const void *e, int n,
+ * pairs: mean_i of the loss selected by loss_kind (see qxd_train_params.loss) with
+ * rhat = r_i/|r_i|, ehat = e_i/|r_i|.  r, e: device arrays of n F32 even half
+ * fields, one after another.  Synchronous. */
+qxd_status qxd_nn_loss_grad(qxd_handle *h, qxd_nn *net, const void *r, const void *e, int n, int loss_kind,
                             double *loss, float *grad, void *stream);
 
 /* Harvest training pairs from an FP64 GCR solve of D_hat x = bhat (no
@@ -241,7 +250,10 @@ qxd_status qxd_nn_loss_grad(qxd_handle *h, qxd_nn *net, const void *r, const voi
 qxd_status qxd_nn_harvest(qxd_handle *h, const void *b, int npairs, void *r_out, void *e_out,
                           int *n_harvested, void *stream);
 
-/* Adam training on pairs (r, e) as above; synchronous. */
+/* Adam training on pairs (r, e) as above, all taken on the handle's current
+ * gauge field and flavour (loss 1 applies that D_hat); synchronous.  Training on
+ * several fields is a loop over fields, one call per field and pass: the Adam
+ * state persists in the network between calls. */
 qxd_status qxd_nn_train(qxd_handle *h, qxd_nn *net, const qxd_train_params *p, const void *r, const void *e,
                         int npairs, qxd_train_stats *stats, void *stream);
 

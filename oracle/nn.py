@@ -9,9 +9,12 @@ convolution layers whose taps follow the C* neighbour map, real channels
   channel ``2 c + 0`` = Re, ``2 c + 1`` = Im of component ``c = 3 spin + colour``.
 * Output: the 24 channels of the last layer read back as a spinor, kept on the
   even sites only.
-* Preconditioner use: ``M(r) = |r| N(r / |r|)``.
-* Training loss over a batch: ``mean_i |N(rhat_i) - ehat_i|^2 / |ehat_i|^2``
-  with ``rhat = r / |r|``, ``ehat = e / |r|``.
+* Preconditioner use: ``M(r) = |r| (N(r / |r|) + skip r / |r|)`` (skip 0: the
+  plain network; the linear skip has no weights).
+* Training loss over a batch, with ``rhat = r / |r|``, ``ehat = e / |r|``:
+  kind 0: ``mean_i |N(rhat_i) - ehat_i|^2 / |ehat_i|^2``;
+  kind 1: ``mean_i |D_hat (N(rhat_i) - ehat_i)|^2 / |rhat_i|^2``, the same error
+  in the D_hat^+ D_hat norm (the gradient at the output is 2 D_hat^+ D_hat (y - ehat)).
 
 Weights ``W[l]`` have shape (81, cout, cin); tap = 27(d0+1)+9(d1+1)+3(d2+1)+(d3+1).
 Backward is the chain rule written out layer by layer: the data gradient of
@@ -42,20 +45,24 @@ def unembed(o, y):
     return out
 
 
-def forward(o, W, r):
-    """N(r) and the activations needed by the backward pass."""
+def forward(o, W, r, skip=0.0):
+    """N(r) + skip r and the activations needed by the backward pass."""
     h0 = embed(o, r)
     a1 = o.nn_conv(W[0], h0)
     h1 = np.maximum(a1, 0.0)
     a2 = o.nn_conv(W[1], h1)
     h2 = np.maximum(a2, 0.0)
     a3 = o.nn_conv(W[2], h2)
-    return unembed(o, a3), (h0, a1, h1, a2, h2, a3)
+    y = unembed(o, a3)
+    if skip:
+        y = y + skip * r * (o.parity() == 0)[:, None, None]
+    return y, (h0, a1, h1, a2, h2, a3)
 
 
-def apply_precond(o, W, r):
+def apply_precond(o, W, r, skip=0.0):
+    """M(r) = |r| (N(r/|r|) + skip r/|r|)."""
     n = np.linalg.norm(r)
-    y, _ = forward(o, W, r / n)
+    y, _ = forward(o, W, r / n, skip)
     return n * y
 
 
@@ -71,7 +78,7 @@ def backward(o, W, acts, gy):
     return [dW1, dW2, dW3]
 
 
-def loss_and_grad(o, W, rs, es):
+def loss_and_grad(o, W, rs, es, kind=0, skip=0.0):
     """Batch loss and its weight gradients; ``rs``, ``es`` are lists of spinors."""
     B = len(rs)
     L = 0.0
@@ -79,11 +86,17 @@ def loss_and_grad(o, W, rs, es):
     for r, e in zip(rs, es):
         n = np.linalg.norm(r)
         rh, eh = r / n, e / n
-        y, acts = forward(o, W, rh)
+        y, acts = forward(o, W, rh, skip)
         d = y - eh
-        ne2 = np.vdot(eh, eh).real
-        L += np.vdot(d, d).real / ne2 / B
-        gy = 2.0 * d / ne2 / B
+        if kind == 0:
+            ne2 = np.vdot(eh, eh).real
+            L += np.vdot(d, d).real / ne2 / B
+            gy = 2.0 * d / ne2 / B
+        else:
+            v = o.schur(d)
+            nr2 = np.vdot(rh, rh).real
+            L += np.vdot(v, v).real / nr2 / B
+            gy = 2.0 * o.schur(v, dagger=True) / nr2 / B
         for k, g in enumerate(backward(o, W, acts, gy)):
             grads[k] += g
     return L, grads

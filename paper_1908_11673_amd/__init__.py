@@ -62,7 +62,7 @@ class qxd_solver_stats(ctypes.Structure):
 class qxd_train_params(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
-                ("holdout", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("holdout", ctypes.c_int), ("seed", ctypes.c_uint64), ("loss", ctypes.c_int)]
 
 
 class qxd_train_stats(ctypes.Structure):
@@ -96,9 +96,10 @@ _SIGNATURES = {
     "qxd_nn_create": ([_P, ctypes.POINTER(_P)], _I),
     "qxd_nn_destroy": ([_P], _I),
     "qxd_nn_set_weights": ([_P, _P], _I),
+    "qxd_nn_set_skip": ([_P, _D], _I),
     "qxd_nn_get_weights": ([_P, _P], _I),
     "qxd_nn_apply": ([_P, _P, _P, _P, _P], _I),
-    "qxd_nn_loss_grad": ([_P, _P, _P, _P, _I, ctypes.POINTER(_D), _P, _P], _I),
+    "qxd_nn_loss_grad": ([_P, _P, _P, _P, _I, _I, ctypes.POINTER(_D), _P, _P], _I),
     "qxd_nn_harvest": ([_P, _P, _I, _P, _P, ctypes.POINTER(_I), _P], _I),
     "qxd_nn_train": ([_P, _P, ctypes.POINTER(qxd_train_params), _P, _P, _I, ctypes.POINTER(qxd_train_stats), _P],
                      _I),
@@ -263,6 +264,10 @@ def qxd_nn_destroy(net):
     _check(load().qxd_nn_destroy(net), "qxd_nn_destroy")
 
 
+def qxd_nn_set_skip(net, skip):
+    _check(load().qxd_nn_set_skip(net, float(skip)), "qxd_nn_set_skip")
+
+
 def qxd_nn_set_weights(net, w):
     w = np.ascontiguousarray(w, dtype=np.float32)
     assert w.size == NN_NWEIGHTS
@@ -279,11 +284,11 @@ def qxd_nn_apply(h, net, out_e, in_e, stream=None):
     _check(load().qxd_nn_apply(h, net, _ptr(out_e), _ptr(in_e), _stream(stream)), "qxd_nn_apply")
 
 
-def qxd_nn_loss_grad(h, net, r, e, n, stream=None):
+def qxd_nn_loss_grad(h, net, r, e, n, loss_kind=0, stream=None):
     loss = ctypes.c_double()
     g = np.empty(NN_NWEIGHTS, dtype=np.float32)
-    _check(load().qxd_nn_loss_grad(h, net, _ptr(r), _ptr(e), int(n), ctypes.byref(loss), g.ctypes.data,
-                                   _stream(stream)), "qxd_nn_loss_grad")
+    _check(load().qxd_nn_loss_grad(h, net, _ptr(r), _ptr(e), int(n), int(loss_kind), ctypes.byref(loss),
+                                   g.ctypes.data, _stream(stream)), "qxd_nn_loss_grad")
     return loss.value, g
 
 
@@ -294,9 +299,9 @@ def qxd_nn_harvest(h, b, npairs, r_out, e_out, stream=None):
     return got.value
 
 
-def train_params(epochs=10, batch=8, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, holdout=0, seed=0):
+def train_params(epochs=10, batch=8, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, holdout=0, seed=0, loss=1):
     return qxd_train_params(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps), int(holdout),
-                            int(seed))
+                            int(seed), int(loss))
 
 
 def qxd_nn_train(h, net, params, r, e, npairs, stream=None):

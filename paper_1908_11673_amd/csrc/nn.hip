@@ -44,9 +44,11 @@ struct qxd_nn {
   uint16_t* wa = nullptr;  // bf16 adjoint weights [3][81 reversed][32 cin][32 cout]
   float *m = nullptr, *v = nullptr, *grad = nullptr;
   int64_t t = 0;
+  float skip = 0.f;        // M(r) = |r| (N(rhat) + skip rhat)
   uint16_t *a0 = nullptr, *a1 = nullptr, *a2 = nullptr;  // [V][32]
   uint16_t *g3 = nullptr, *gA = nullptr, *gB = nullptr;  // training: [V][32]
   float* y = nullptr;      // training: raw network output (even half field, F32)
+  float *dv = nullptr, *dz = nullptr;  // training, residual loss: D_hat u and D_hat^+ D_hat u
   float* part = nullptr;   // weight-gradient partials
   int nchunk = 0;
 };
@@ -87,11 +89,15 @@ enum { EPI_RELU = 0, EPI_SPINOR = 1, EPI_MASK = 2 };
 // EPI_MASK:   out_act[q][c] = mask[q][c] > 0 ? bf16(acc) : 0
 // SPARSE_IN: the input vanishes on odd sites (layer 1): taps landing on odd
 // sites are skipped when the whole wave has one parity.
+// EPI_SPINOR also adds skip_coef * rin (rin: F32 even half field, may be null),
+// with skip_coef = skip when the output is scaled by |r| (scal given), else
+// skip / sqrt(scal2[i_s2]) (the input is normalised at the output of training).
 template <int EPI, bool SPARSE_IN>
 __global__ __launch_bounds__(256) void k_conv(Geo g, const uint16_t* __restrict__ in, const uint16_t* __restrict__ W,
                                               int nout, uint16_t* __restrict__ out_act, float* __restrict__ out_f,
                                               const uint16_t* __restrict__ mask, const double* __restrict__ scal,
-                                              int i_s) {
+                                              int i_s, const float* __restrict__ rin, float skip,
+                                              const double* __restrict__ scal2, int i_s2) {
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int qbase = (blockIdx.x * 4 + wave) * 64;
   if (qbase >= nout) return;
@@ -154,8 +160,9 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, const uint16_t* __restrict_
       }
     }
   }
-  float scale = 1.0f;
+  float scale = 1.0f, skc = 0.0f;
   if (EPI == EPI_SPINOR && scal) scale = (float)sqrt(scal[i_s]);
+  if (EPI == EPI_SPINOR && rin) skc = scal2 ? (float)(skip / sqrt(scal2[i_s2])) : skip;
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -173,7 +180,10 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, const uint16_t* __restrict_
                                               ? f2bf(vv)
                                               : (uint16_t)0;
         } else {
-          if (c < 24) out_f[((size_t)(c >> 2) * g.Ve + q) * 4 + (c & 3)] = vv * scale;
+          if (c < 24) {
+            size_t o = ((size_t)(c >> 2) * g.Ve + q) * 4 + (c & 3);
+            out_f[o] = rin ? vv * scale + skc * rin[o] : vv * scale;
+          }
         }
       }
 }
@@ -248,6 +258,36 @@ __global__ __launch_bounds__(256) void k_nn_lossgrad(Geo g, const float4* __rest
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// u = y - e / |r| (in place in y)
+__global__ __launch_bounds__(256) void k_nn_err(int Ve, float4* __restrict__ y, const float4* __restrict__ e,
+                                                const double* __restrict__ scal, int i_r2) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)6 * Ve) return;
+  float ir = (float)(1.0 / sqrt(scal[i_r2]));
+  float4 a = y[i], b = e[i];
+  y[i] = make_float4(a.x - ir * b.x, a.y - ir * b.y, a.z - ir * b.z, a.w - ir * b.w);
+}
+
+// g3 on the even sites = f * z (F32 even half field), channels 24..31 zero
+__global__ __launch_bounds__(256) void k_nn_embed_grad(int Ve, const float4* __restrict__ z, float f,
+                                                       uint16_t* __restrict__ g3) {
+  int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= Ve) return;
+  uint16_t v[NN_C];
+  for (int c = 0; c < NN_C; ++c) v[c] = 0;
+  for (int j = 0; j < 6; ++j) {
+    float4 x = z[(size_t)j * Ve + q];
+    v[4 * j] = f2bf(f * x.x);
+    v[4 * j + 1] = f2bf(f * x.y);
+    v[4 * j + 2] = f2bf(f * x.z);
+    v[4 * j + 3] = f2bf(f * x.w);
+  }
+  uint4* o = reinterpret_cast<uint4*>(g3 + (size_t)q * NN_C);
+  for (int k = 0; k < 4; ++k)
+    o[k] = make_uint4(v[8 * k] | (v[8 * k + 1] << 16), v[8 * k + 2] | (v[8 * k + 3] << 16),
+                      v[8 * k + 4] | (v[8 * k + 5] << 16), v[8 * k + 6] | (v[8 * k + 7] << 16));
 }
 
 // weight-gradient partials: part[chunk][tap][co][ci] = sum_{q in chunk} gq[q][co] in[q + d][ci]
@@ -353,23 +393,24 @@ static qxd_status nn_repack(qxd_nn* net, hipStream_t s) {
 
 static void conv_launch(qxd_handle* h, int layer, const uint16_t* in, const uint16_t* W, int nout, int epi,
                         uint16_t* out_act, float* out_f, const uint16_t* mask, const double* scal, int i_s,
-                        hipStream_t s) {
+                        hipStream_t s, const float* rin = nullptr, float skip = 0.f, const double* scal2 = nullptr,
+                        int i_s2 = 0) {
   int waves = div_up(nout, 64);
   dim3 grid(div_up(waves, 4));
   const uint16_t* wl = W + (size_t)layer * NN_LAYER_W;
   if (epi == EPI_RELU) {
     if (layer == 0)
       hipLaunchKernelGGL((k_conv<EPI_RELU, true>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
-                         scal, i_s);
+                         scal, i_s, rin, skip, scal2, i_s2);
     else
       hipLaunchKernelGGL((k_conv<EPI_RELU, false>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
-                         scal, i_s);
+                         scal, i_s, rin, skip, scal2, i_s2);
   } else if (epi == EPI_SPINOR) {
     hipLaunchKernelGGL((k_conv<EPI_SPINOR, false>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
-                       scal, i_s);
+                       scal, i_s, rin, skip, scal2, i_s2);
   } else {
     hipLaunchKernelGGL((k_conv<EPI_MASK, false>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
-                       scal, i_s);
+                       scal, i_s, rin, skip, scal2, i_s2);
   }
 }
 
@@ -391,6 +432,8 @@ static qxd_status nn_alloc_train(qxd_nn* net, hipStream_t s) {
   if (hipMalloc(&net->g3, bytes) != hipSuccess || hipMalloc(&net->gA, bytes) != hipSuccess ||
       hipMalloc(&net->gB, bytes) != hipSuccess ||
       hipMalloc(&net->y, (size_t)h->Ve * 24 * sizeof(float)) != hipSuccess ||
+      hipMalloc(&net->dv, (size_t)h->Ve * 24 * sizeof(float)) != hipSuccess ||
+      hipMalloc(&net->dz, (size_t)h->Ve * 24 * sizeof(float)) != hipSuccess ||
       hipMalloc(&net->part, (size_t)net->nchunk * NN_TAPS * NN_C * NN_C * sizeof(float)) != hipSuccess)
     return QXD_ENOMEM;
   // the odd half of g3 is never written: zero once
@@ -408,7 +451,8 @@ static qxd_status nn_forward(qxd_handle* h, qxd_nn* net, const float4* r, float*
   conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s);
   conv_launch(h, 1, net->a1, net->wf, (int)h->V, EPI_RELU, net->a2, nullptr, nullptr, nullptr, 0, s);
   conv_launch(h, 2, net->a2, net->wf, (int)h->Ve, EPI_SPINOR, nullptr, out, nullptr, with_norm ? h->scal : nullptr,
-              S_NN, s);
+              S_NN, s, net->skip != 0.f ? reinterpret_cast<const float*>(r) : nullptr, net->skip,
+              with_norm ? nullptr : h->scal, S_NN);
   QXD_HIP(hipGetLastError());
   return QXD_OK;
 }
@@ -423,7 +467,7 @@ qxd_status nn_apply_internal(qxd_handle* h, qxd_nn* net, float4* out_e, const fl
 // slot + 1 = |e|^2, slot + 2 = |N(rhat) - ehat|^2 |e|^2 / |r|^2... stored raw as
 // |N(rhat) - e/|r||^2; the pair loss is scal[slot+2] scal[slot] / scal[slot+1].
 static qxd_status nn_pair(qxd_handle* h, qxd_nn* net, const float4* r, const float4* e, double invB, int slot,
-                          bool backward, hipStream_t s) {
+                          int kind, bool backward, hipStream_t s) {
   size_t nw = (size_t)6 * h->Ve;
   blas_norm2<float4>(h, r, nw, h->scal + slot, s);
   blas_norm2<float4>(h, e, nw, h->scal + slot + 1, s);
@@ -431,12 +475,25 @@ static qxd_status nn_pair(qxd_handle* h, qxd_nn* net, const float4* r, const flo
   hipLaunchKernelGGL(k_nn_embed, dim3(div_up(2 * h->Ve, 256)), dim3(256), 0, s, h->geo, r, h->scal, slot, net->a0);
   conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s);
   conv_launch(h, 1, net->a1, net->wf, (int)h->V, EPI_RELU, net->a2, nullptr, nullptr, nullptr, 0, s);
-  conv_launch(h, 2, net->a2, net->wf, (int)h->Ve, EPI_SPINOR, nullptr, net->y, nullptr, nullptr, 0, s);
+  conv_launch(h, 2, net->a2, net->wf, (int)h->Ve, EPI_SPINOR, nullptr, net->y, nullptr, nullptr, 0, s,
+              net->skip != 0.f ? reinterpret_cast<const float*>(r) : nullptr, net->skip, h->scal, slot);
   // output gradient and loss partials
   int G = div_up(h->Ve, 256);
-  hipLaunchKernelGGL(k_nn_lossgrad, dim3(G), dim3(256), 0, s, h->geo, (const float4*)net->y, e, h->scal, slot,
-                     slot + 1, invB, net->g3, h->partial);
-  launch_final_sum(h->partial, G, 1, G, h->scal + slot + 2, s);
+  if (kind == 0) {
+    hipLaunchKernelGGL(k_nn_lossgrad, dim3(G), dim3(256), 0, s, h->geo, (const float4*)net->y, e, h->scal, slot,
+                       slot + 1, invB, net->g3, h->partial);
+    launch_final_sum(h->partial, G, 1, G, h->scal + slot + 2, s);
+  } else {
+    // u = y - ehat;  v = D_hat u (|v|^2 -> slot + 2);  g = (2/B) D_hat^+ v
+    hipLaunchKernelGGL(k_nn_err, dim3(div_up(6 * h->Ve, 256)), dim3(256), 0, s, (int)h->Ve, (float4*)net->y, e,
+                       h->scal, slot);
+    QXD_TRY(qxd_schur_apply(h, QXD_F32, 0, net->dv, net->y, h->scal + slot + 2, s));
+    if (backward) {
+      QXD_TRY(qxd_schur_apply(h, QXD_F32, 1, net->dz, net->dv, nullptr, s));
+      hipLaunchKernelGGL(k_nn_embed_grad, dim3(G), dim3(256), 0, s, (int)h->Ve, (const float4*)net->dz,
+                         (float)(2.0 * invB), net->g3);
+    }
+  }
   if (!backward) return QXD_OK;
   // layer 3: weight gradient over the even sites, data gradient masked by a2 > 0
   dim3 wg(net->nchunk, div_up(NN_TAPS, 4));
@@ -458,8 +515,9 @@ static qxd_status nn_pair(qxd_handle* h, qxd_nn* net, const float4* r, const flo
   return QXD_OK;
 }
 
-static double pair_loss(const qxd_handle* h, int slot) {
-  return h->scal_host[slot + 2] * h->scal_host[slot] / h->scal_host[slot + 1];
+static double pair_loss(const qxd_handle* h, int slot, int kind) {
+  if (kind == 0) return h->scal_host[slot + 2] * h->scal_host[slot] / h->scal_host[slot + 1];
+  return h->scal_host[slot + 2];
 }
 
 extern "C" qxd_status qxd_nn_create(qxd_handle* h, qxd_nn** out) {
@@ -492,10 +550,16 @@ extern "C" qxd_status qxd_nn_destroy(qxd_nn* net) {
   if (!net) return QXD_EINVAL;
   (void)hipDeviceSynchronize();
   void* ptrs[] = {net->w, net->wf, net->wa, net->m, net->v, net->grad, net->a0, net->a1,
-                  net->a2, net->g3, net->gA, net->gB, net->y, net->part};
+                  net->a2, net->g3, net->gA, net->gB, net->y, net->part, net->dv, net->dz};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete net;
+  return QXD_OK;
+}
+
+extern "C" qxd_status qxd_nn_set_skip(qxd_nn* net, double skip) {
+  if (!net || !std::isfinite(skip)) return QXD_EINVAL;
+  net->skip = (float)skip;
   return QXD_OK;
 }
 
@@ -524,19 +588,21 @@ extern "C" qxd_status qxd_nn_apply(qxd_handle* h, qxd_nn* net, void* out_e, cons
   return nn_apply_internal(h, net, (float4*)out_e, (const float4*)in_e, as_stream(stream));
 }
 
-extern "C" qxd_status qxd_nn_loss_grad(qxd_handle* h, qxd_nn* net, const void* r, const void* e, int n, double* loss,
-                                       float* grad, void* stream) {
-  if (!h || !net || !r || !e || n < 1 || net->h != h) return QXD_EINVAL;
+extern "C" qxd_status qxd_nn_loss_grad(qxd_handle* h, qxd_nn* net, const void* r, const void* e, int n,
+                                       int loss_kind, double* loss, float* grad, void* stream) {
+  if (!h || !net || !r || !e || n < 1 || net->h != h || loss_kind < 0 || loss_kind > 1) return QXD_EINVAL;
+  if (loss_kind == 1 && !h->has_inverse) return QXD_ESTATE;
   hipStream_t s = as_stream(stream);
   QXD_TRY(nn_alloc_train(net, s));
   QXD_HIP(hipMemsetAsync(net->grad, 0, QXD_NN_NWEIGHTS * 4, s));
   size_t half = (size_t)6 * h->Ve;
   double total = 0.0;
   for (int i = 0; i < n; ++i) {
-    QXD_TRY(nn_pair(h, net, (const float4*)r + i * half, (const float4*)e + i * half, 1.0 / n, S_NN, true, s));
+    QXD_TRY(nn_pair(h, net, (const float4*)r + i * half, (const float4*)e + i * half, 1.0 / n, S_NN, loss_kind, true,
+                    s));
     QXD_HIP(hipMemcpyAsync(h->scal_host + S_NN, h->scal + S_NN, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     QXD_HIP(hipStreamSynchronize(s));
-    total += pair_loss(h, S_NN) / n;
+    total += pair_loss(h, S_NN, loss_kind) / n;
   }
   if (loss) *loss = total;
   if (grad) {
@@ -559,7 +625,8 @@ extern "C" qxd_status qxd_nn_train(qxd_handle* h, qxd_nn* net, const qxd_train_p
   auto t0 = std::chrono::steady_clock::now();
   if (!h || !net || !p || !r || !e || net->h != h) return QXD_EINVAL;
   int ntrain = npairs - std::max(0, p->holdout);
-  if (ntrain < 1 || p->batch < 1 || p->batch > 64 || p->epochs < 1) return QXD_EINVAL;
+  if (ntrain < 1 || p->batch < 1 || p->batch > 64 || p->epochs < 1 || p->loss < 0 || p->loss > 1) return QXD_EINVAL;
+  if (p->loss == 1 && !h->has_inverse) return QXD_ESTATE;
   hipStream_t s = as_stream(stream);
   QXD_TRY(nn_alloc_train(net, s));
   size_t half = (size_t)6 * h->Ve;
@@ -578,7 +645,7 @@ extern "C" qxd_status qxd_nn_train(qxd_handle* h, qxd_nn* net, const qxd_train_p
       QXD_HIP(hipMemsetAsync(net->grad, 0, QXD_NN_NWEIGHTS * 4, s));
       for (int k = 0; k < nb; ++k) {
         int idx = order[b0 + k];
-        QXD_TRY(nn_pair(h, net, R + idx * half, E + idx * half, 1.0 / nb, base + 3 * k, true, s));
+        QXD_TRY(nn_pair(h, net, R + idx * half, E + idx * half, 1.0 / nb, base + 3 * k, p->loss, true, s));
       }
       net->t++;
       float c1 = 1.f - (float)std::pow(p->beta1, (double)net->t), c2 = 1.f - (float)std::pow(p->beta2, (double)net->t);
@@ -588,7 +655,7 @@ extern "C" qxd_status qxd_nn_train(qxd_handle* h, qxd_nn* net, const qxd_train_p
       QXD_TRY(nn_repack(net, s));
       QXD_HIP(hipMemcpyAsync(h->scal_host + base, h->scal + base, 3 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
       QXD_HIP(hipStreamSynchronize(s));
-      for (int k = 0; k < nb; ++k) ep_loss += pair_loss(h, base + 3 * k);
+      for (int k = 0; k < nb; ++k) ep_loss += pair_loss(h, base + 3 * k, p->loss);
       st.steps++;
     }
     ep_loss /= ntrain;
@@ -599,10 +666,10 @@ extern "C" qxd_status qxd_nn_train(qxd_handle* h, qxd_nn* net, const qxd_train_p
   double hl = 0.0;
   int nh = npairs - ntrain;
   for (int i = 0; i < nh; ++i) {
-    QXD_TRY(nn_pair(h, net, R + (ntrain + i) * half, E + (ntrain + i) * half, 1.0, base, false, s));
+    QXD_TRY(nn_pair(h, net, R + (ntrain + i) * half, E + (ntrain + i) * half, 1.0, base, p->loss, false, s));
     QXD_HIP(hipMemcpyAsync(h->scal_host + base, h->scal + base, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     QXD_HIP(hipStreamSynchronize(s));
-    hl += pair_loss(h, base) / nh;
+    hl += pair_loss(h, base, p->loss) / nh;
   }
   st.holdout_loss = nh > 0 ? hl : 0.0;
   st.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

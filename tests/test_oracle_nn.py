@@ -47,8 +47,11 @@ def test_conv_adjoint_and_weight_gradient():
     assert abs(np.sum(g * o.nn_conv(dW, h)) - np.sum(dW * o.nn_conv_wgrad(g, h, 5, 7))) < 1e-11
 
 
-def test_network_gradients_by_central_differences():
+@pytest.mark.parametrize("kind", [0, 1])
+def test_network_gradients_by_central_differences(kind):
     o = lattice()
+    o.set_gauge_physical(sg.gauge_su3(3, 0.3, o.Vphys), sg.gauge_u1(3, 0.3, o.Vphys))
+    o.set_flavour(**sg.FLAVOURS["d"])
     W = weights(11, scale=1.5)
     par = o.parity()
     rs, es = [], []
@@ -59,7 +62,7 @@ def test_network_gradients_by_central_differences():
         e[par == 1] = 0
         rs.append(r)
         es.append(e)
-    L0, grads = nn.loss_and_grad(o, W, rs, es)
+    L0, grads = nn.loss_and_grad(o, W, rs, es, kind)
     rng = np.random.default_rng(0)
     h = 1e-6
     for layer in range(3):
@@ -69,8 +72,10 @@ def test_network_gradients_by_central_differences():
             Wm = [w.copy() for w in W]
             Wp[layer][idx] += h
             Wm[layer][idx] -= h
-            fd = (nn.loss_and_grad(o, Wp, rs, es)[0] - nn.loss_and_grad(o, Wm, rs, es)[0]) / (2 * h)
-            assert abs(fd - grads[layer][idx]) <= 1e-7 * max(1e-3, abs(grads[layer][idx])), (layer, idx)
+            fd = (nn.loss_and_grad(o, Wp, rs, es, kind)[0] - nn.loss_and_grad(o, Wm, rs, es, kind)[0]) / (2 * h)
+            # central differences: truncation O(h^2), rounding about 1e-16 L0 / h
+            tol = 1e-7 * abs(grads[layer][idx]) + 1e-9 * max(1.0, L0)
+            assert abs(fd - grads[layer][idx]) <= tol, (layer, idx)
 
 
 def test_network_is_positively_homogeneous_and_translation_equivariant():
