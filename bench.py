@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--nn-fields", type=int, default=10, help="fields for the network training (0: no network)")
+    ap.add_argument("--nn-epochs", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU path (time-slab halo exchange over xGMI) "
@@ -196,7 +198,7 @@ def main():
     }
 
     if not args.no_solve:
-        result["time_to_solution"] = solve_leg(qxd, torch, lats, w)
+        result["time_to_solution"] = solve_leg(qxd, torch, lats, w, flavours, args.nn_fields, args.nn_epochs)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -228,32 +230,63 @@ def copy_calibration(torch):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
-def solve_leg(qxd, torch, lats, w):
+def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs):
+    """Time to a true FP64 residual 1e-10 on the benchmark lattice, one Gaussian
+    source per flavour: FP64 CG against FP32-inner FGCR, bf16-link-inner FGCR,
+    and FP32-inner FGCR preconditioned by a network trained (per flavour) on pairs
+    harvested from seeded 32 x 16^3 fields with the same statistics."""
     import synthgen as sg
+    from paper_1908_11673_amd import learned
+    c3 = sg.WORKLOADS["c3"]
     out = {}
     b = sg.spinor(w["source_seed"] + 1, lats[0].V)
-    for lat, name in zip(lats, ("qhat-2", "qhat+4")):
+    for lat, flav, name in zip(lats, flavours, ("qhat-2", "qhat+4")):
+        res = {}
+        net = None
+        if nn_fields > 0:
+            t0 = time.perf_counter()
+            wts, skip, info = learned.harvest_and_train(c3["L"], c3["cstar"], flav,
+                                                        gauge_seeds=list(range(3000, 3000 + nn_fields)),
+                                                        sigma_su3=w["sigma_su3"], sigma_u1=w["sigma_u1"], sources=8,
+                                                        pairs_per_source=10, epochs=nn_epochs)
+            net = learned.make_network(lat, wts, skip)
+            res["network_training"] = {"pairs": info["pairs"], "harvest_s": round(info["harvest_s"], 2),
+                                       "train_s": round(info["train_s"], 2),
+                                       "loss_first_last": [round(info["loss_history"][0], 4),
+                                                           round(info["loss_history"][-1], 4)],
+                                       "lattice": "32x16^3 physical, C* 3", "fields": nn_fields,
+                                       "epochs": nn_epochs, "skip": skip}
+            log("%s network: %d pairs, harvest %.1f s, train %.1f s, loss %.3f -> %.3f" % (
+                name, info["pairs"], info["harvest_s"], info["train_s"], info["loss_history"][0],
+                info["loss_history"][-1]))
         bd = lat.pack(torch.from_numpy(b).cuda())
         x = lat.field(qxd.F64, full=True)
-        res = {}
-        for tag, fn in (
-                ("cg_f64", lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, check_every=8), x, bd,
-                                                    check=False)),
-                ("fgcr_f32_in_f64", lambda: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32,
-                                                                                        nkv=16), None, x, bd,
-                                                               check=False)),
+        legs = [("cg_f64", lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, check_every=8), x, bd,
+                                                     check=False)),
+                ("fgcr_f32_in_f64", lambda: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10,
+                                                                                        inner_prec=qxd.F32),
+                                                               None, x, bd, check=False)),
                 ("fgcr_bf16links_in_f64", lambda: qxd.qxd_solve_fgcr(
-                    lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.BF16, nkv=16), None, x, bd, check=False))):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = fn()
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3
-            res[tag] = {"ms": round(ms, 2), "status": st["status"], "iterations": st["inner_it"],
-                        "outer": st["outer_it"], "schur_applies": st["schur_applies"],
+                    lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.BF16), None, x, bd, check=False))]
+        if net is not None:
+            legs.append(("fgcr_f32_nn_in_f64", lambda: qxd.qxd_solve_fgcr(
+                lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32), net, x, bd, check=False)))
+        for tag, fn in legs:
+            times = []
+            for rep in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = fn()
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - t0) * 1e3)
+            res[tag] = {"ms_median": round(float(np.median(times)), 2), "status": st["status"],
+                        "iterations": st["inner_it"], "outer": st["outer_it"], "schur_applies": st["schur_applies"],
+                        "nn_applies": st["nn_applies"], "fell_back": st["fell_back"],
                         "true_residual": st["true_residual"]}
-            log("solve %s %s: %.1f ms, %d it, res %.2e, status %d" % (name, tag, ms, st["inner_it"],
+            log("solve %s %s: %.1f ms, %d it, res %.2e, status %d" % (name, tag, np.median(times), st["inner_it"],
                                                                        st["true_residual"], st["status"]))
+        if net is not None:
+            qxd.qxd_nn_destroy(net)
         out[name] = res
     return out
 

@@ -54,13 +54,17 @@ extern "C" qxd_status qxd_create(const qxd_geom* g, qxd_handle** out) {
   h->geo.L3h = g->L[3] / 2;
   h->geo.Ve = (int)h->Ve;
   h->geo.tchunk = 8;
-  if (const char* e = std::getenv("QXD_TILE_CHUNK")) h->geo.tchunk = std::atoi(e);
+  if (const char* e = std::getenv("QXD_TILE_CHUNK")) {
+    h->geo.tchunk = std::atoi(e);
+    h->tchunk_env = true;
+  }
+  if (const char* e = std::getenv("QXD_STREAM_KERNELS")) h->stream_kernels = std::atoi(e) != 0;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return QXD_EHIP;
   }
   h->npartial = (size_t)QXD_MAX_PARTIAL;
-  if ((size_t)div_up(h->Ve, QXD_BLOCK) > h->npartial) h->npartial = (size_t)div_up(h->Ve, QXD_BLOCK);
+  if ((size_t)div_up(h->Ve, 64) > h->npartial) h->npartial = (size_t)div_up(h->Ve, 64);
   if (hipMalloc(&h->partial, h->npartial * sizeof(double)) != hipSuccess ||
       hipMalloc(&h->scal, QXD_NSCAL * sizeof(double)) != hipSuccess ||
       hipHostMalloc(&h->scal_host, QXD_NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess) {

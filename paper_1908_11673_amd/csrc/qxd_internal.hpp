@@ -318,6 +318,8 @@ struct qxd_handle {
   double* scal = nullptr;     // [QXD_NSCAL] device scalars
   double* scal_host = nullptr;  // pinned mirror
   size_t npartial = 0;        // doubles in `partial`
+  bool tchunk_env = false;    // walk chunk fixed by QXD_TILE_CHUNK
+  bool stream_kernels = false; // time-streaming Schur kernels (measured slower; kept for tuning)
   // solver workspaces (grow-only), indexed by role
   void* ws[64] = {};
   size_t ws_bytes[64] = {};
