@@ -191,7 +191,8 @@ def main():
                    "even_sites": Ve, "flavours": [{"qhat": f["qhat"], "kappa": f["kappa"]} for f in flavours],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(ach64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach64 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach64 / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic("dhat_f64") if args.workload == "c1" else None,
                      "kernel": "D_hat FP64 (k_schur1 + k_schur2)", "ms_per_launch": round(ms64, 4)},
         "dhat_fp32": {"ms": round(ms32, 4), "achieved_gbs": round(ach32, 1), "frac": round(ach32 / HBM_PEAK_GBS, 4)},
         "copy_kernel_gbs": round(copy_gbs, 1),
@@ -206,6 +207,30 @@ def main():
     print(json.dumps(result), flush=True)
     for lat in lats:
         lat.close()
+
+
+TRAFFIC_SOURCES = ("paper_1908_11673_amd/csrc/dirac.hip", "paper_1908_11673_amd/csrc/qxd_internal.hpp",
+                   "paper_1908_11673_amd/build.py")
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "dhat_schur_c1.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    for line in open(path):
+        if line.startswith("traffic-record:"):
+            kv = dict(item.split("=", 1) for item in line.split()[1:])
+            if kv.get("kernel") == kernel and kv.get("sources_sha256") == h.hexdigest():
+                return int(kv["bytes_per_launch"])
+    return None
 
 
 def copy_calibration(torch):

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -51,6 +52,8 @@ struct qxd_nn {
   float *dv = nullptr, *dz = nullptr;  // training, residual loss: D_hat u and D_hat^+ D_hat u
   float* part = nullptr;   // weight-gradient partials
   int nchunk = 0;
+  bool blk = false;        // block-tiled convolutions (else per-site gathers)
+  int bk[7] = {0, 0, 0, 0, 0, 0, 0};  // B0..B3, n1..n3 of the block tiling
 };
 
 static const int kWgChunk = 2048;  // sites per weight-gradient workgroup
@@ -186,6 +189,268 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, const uint16_t* __restrict_
           }
         }
       }
+}
+
+// ---------------------------------------------------------------------------
+// Block-tiled convolution.  A workgroup of 8 waves owns a B0 x B1 x B2 x B3
+// block of 512 sites (every B even, dividing the extended extents, so the
+// block origin is an even site and local parity equals lattice parity).  The
+// block and its one-site halo are staged once in LDS (64 bytes per site, the
+// four 16-byte chunks XOR-swizzled against LDS bank conflicts), every tap then
+// reads its MFMA operands from LDS at a constant offset: with the 3^4 stencil
+// each activation is fetched from memory about (B+2)^4 / B^4 ~ 4 times instead
+// of 81 times.  The halo follows the C* neighbour map (a crossing of the k <=
+// cstar boundaries moves x1 by L1; two crossings cancel).  Rows of one MFMA
+// tile share a parity, so with an input that vanishes on odd sites (SPARSE_IN)
+// the taps landing on odd sites are skipped for whole waves, and odd halo sites
+// are not loaded.  EVEN_OUT computes the even sites only (last layer).
+struct NnBlk {
+  int B0, B1, B2, B3;  // block extents
+  int H1, H2, H3;      // halo extents B + 2 (H0 = B0 + 2)
+  int npos;            // halo positions
+  int n1, n2, n3;      // blocks along directions 1..3
+};
+
+#define NN_BLK_SITES 512
+#define NN_HALO_MAX 2400  // largest halo admitted (153600 bytes)
+#define NN_LDS_POS 2560   // LDS positions: 5 per thread, 163840 bytes
+
+__device__ inline int nn_lds_off(int pos, int c) { return pos * 64 + ((c ^ ((pos >> 1) & 3)) << 4); }
+
+// j-th site of parity p inside the block: local coordinates
+__device__ inline void nn_blk_site(const NnBlk& bk, int p, int j, int& b0, int& b1, int& b2, int& b3) {
+  int r3 = bk.B3 >> 1;
+  int k = j % r3, line = j / r3;
+  b2 = line % bk.B2;
+  line /= bk.B2;
+  b1 = line % bk.B1;
+  b0 = line / bk.B1;
+  b3 = 2 * k + ((b0 + b1 + b2 + p) & 1);
+}
+
+// Taps a wave of parity-P rows contracts: all 81, or with an input that
+// vanishes on odd sites only those whose neighbours are even (P + |d| even).
+template <bool SPARSE, int P>
+struct NnTapList {
+  int n = 0;
+  int t[81] = {};
+  constexpr NnTapList() {
+    for (int tap = 0; tap < 81; ++tap) {
+      int dist = (tap / 27 != 1) + (tap / 9 % 3 != 1) + (tap / 3 % 3 != 1) + (tap % 3 != 1);
+      if (!SPARSE || ((P + dist) & 1) == 0) t[n++] = tap;
+    }
+  }
+};
+
+// The tap loop of the block kernel, fully unrolled: the weights of tap k + NN_WPF
+// are requested while tap k is contracted, and the LDS operands of tap k + 1
+// are read before the matrix-core instructions of tap k, so neither the L2
+// latency of the weights nor the LDS latency stalls the waves.
+#define NN_WPF 8
+template <bool SPARSE, int P, int RB>
+__device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __restrict__ W, const int* rowpos, int S0,
+                                            int S1, int S2, int lr, int kc, int ch, f4v (&acc)[RB][2]) {
+  constexpr NnTapList<SPARSE, P> TL{};
+  auto tap_off = [&](int tap) {
+    return (tap / 27 - 1) * S0 + (tap / 9 % 3 - 1) * S1 + (tap / 3 % 3 - 1) * S2 + (tap % 3 - 1);
+  };
+  bf16x8 wb[NN_WPF][2];
+#pragma unroll
+  for (int k = 0; k < NN_WPF; ++k)
+    if (k < TL.n) {
+      const uint16_t* wt = W + TL.t[k] * (NN_C * NN_C);
+      wb[k][0] = ld8(wt + lr * NN_C + kc);
+      wb[k][1] = ld8(wt + (16 + lr) * NN_C + kc);
+    }
+  bf16x8 a[RB];
+  {
+    int off = tap_off(TL.t[0]);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) a[rb] = *reinterpret_cast<const bf16x8*>(lds + nn_lds_off(rowpos[rb] + off, ch));
+  }
+#pragma unroll
+  for (int k = 0; k < TL.n; ++k) {
+    bf16x8 w0 = wb[k % NN_WPF][0], w1 = wb[k % NN_WPF][1];
+    if (k + NN_WPF < TL.n) {
+      const uint16_t* wt = W + TL.t[k + NN_WPF] * (NN_C * NN_C);
+      wb[k % NN_WPF][0] = ld8(wt + lr * NN_C + kc);
+      wb[k % NN_WPF][1] = ld8(wt + (16 + lr) * NN_C + kc);
+    }
+    bf16x8 an[RB];
+    if (k + 1 < TL.n) {
+      int off = tap_off(TL.t[k + 1]);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+        an[rb] = *reinterpret_cast<const bf16x8*>(lds + nn_lds_off(rowpos[rb] + off, ch));
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], w0, acc[rb][0], 0, 0, 0);
+      acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], w1, acc[rb][1], 0, 0, 0);
+    }
+    if (k + 1 < TL.n) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) a[rb] = an[rb];
+    }
+  }
+}
+
+template <int EPI, bool SPARSE_IN, bool EVEN_OUT>
+__global__ __launch_bounds__(512) void k_conv_blk(Geo g, NnBlk bk, const uint16_t* __restrict__ in,
+                                                  const uint16_t* __restrict__ W, uint16_t* __restrict__ out_act,
+                                                  float* __restrict__ out_f, const uint16_t* __restrict__ mask,
+                                                  const double* __restrict__ scal, int i_s,
+                                                  const float* __restrict__ rin, float skip,
+                                                  const double* __restrict__ scal2, int i_s2) {
+  __shared__ uint4 lds4[NN_LDS_POS * 4];
+  char* lds = reinterpret_cast<char*>(lds4);
+  const int b = site_tile(blockIdx.x, gridDim.x, -1);
+  int c3 = b % bk.n3, t = b / bk.n3;
+  int c2 = t % bk.n2;
+  t /= bk.n2;
+  int c1 = t % bk.n1, c0 = t / bk.n1;
+  const int o0 = c0 * bk.B0, o1 = c1 * bk.B1, o2 = c2 * bk.B2, o3 = c3 * bk.B3;
+
+  // stage block + halo: one thread per halo position, 64 bytes each; every
+  // load of the thread is issued before the first LDS write
+  // Four consecutive threads move the four 16-byte chunks of one position, so a
+  // wave-wide load covers 16 whole sites; each thread issues all its loads
+  // before its first LDS write.  Positions past the halo and skipped odd sites
+  // are filled with the first site (never read).
+  constexpr int PPT = NN_LDS_POS / 128;
+  static_assert(NN_LDS_POS >= NN_HALO_MAX, "halo staging");
+  const int hc = threadIdx.x & 3;
+  // integer division by the small halo extents through a float reciprocal:
+  // (n + 1/2) / H stays at least 1/(2H) away from an integer for n < 2^12
+  const float rH1 = 1.0f / bk.H1, rH2 = 1.0f / bk.H2, rH3 = 1.0f / bk.H3;
+  uint4 hv[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    int pos = (threadIdx.x >> 2) + 128 * k;
+    bool ok = pos < bk.npos;
+    int r = (int)(((float)pos + 0.5f) * rH3);
+    int h3 = pos - r * bk.H3;
+    int r2 = (int)(((float)r + 0.5f) * rH2);
+    int h2 = r - r2 * bk.H2;
+    int h0 = (int)(((float)r2 + 0.5f) * rH1);
+    int h1 = r2 - h0 * bk.H1;
+    int x0 = o0 + h0 - 1, x1 = o1 + h1 - 1, x2 = o2 + h2 - 1, x3 = o3 + h3 - 1;
+    x0 = x0 < 0 ? x0 + g.Le0 : (x0 >= g.Le0 ? x0 - g.Le0 : x0);
+    x1 = x1 < 0 ? x1 + g.Le1 : (x1 >= g.Le1 ? x1 - g.Le1 : x1);
+    bool mir = false;
+    if (x2 < 0 || x2 >= g.Le2) {
+      x2 = x2 < 0 ? x2 + g.Le2 : x2 - g.Le2;
+      mir = g.cstar >= 2;
+    }
+    if (x3 < 0 || x3 >= g.Le3) {
+      x3 = x3 < 0 ? x3 + g.Le3 : x3 - g.Le3;
+      if (g.cstar >= 3) mir = !mir;
+    }
+    if (mir) x1 = geo_mirror_x1(g, x1);
+    int par = (x0 + x1 + x2 + x3) & 1;
+    ok = ok && !(SPARSE_IN && par);
+    size_t q = ok ? (size_t)par * g.Ve + geo_half(g, x0, x1, x2, x3) : 0;
+    hv[k] = reinterpret_cast<const uint4*>(in + q * NN_C)[hc];
+  }
+#pragma unroll
+  for (int k = 0; k < PPT; ++k)
+    *reinterpret_cast<uint4*>(lds + nn_lds_off((threadIdx.x >> 2) + 128 * k, hc)) = hv[k];
+  __syncthreads();
+
+  constexpr int RB = EVEN_OUT ? 2 : 4;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l & 15, kc = (l >> 4) * 8, ch = l >> 4;
+  const int p = EVEN_OUT ? 0 : (wave >> 2);
+  const int g0 = EVEN_OUT ? wave : (wave & 3), gstep = EVEN_OUT ? 8 : 4;
+  int rowpos[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    int b0, b1, b2, b3;
+    nn_blk_site(bk, p, (g0 + rb * gstep) * 16 + lr, b0, b1, b2, b3);
+    rowpos[rb] = (((b0 + 1) * bk.H1 + b1 + 1) * bk.H2 + b2 + 1) * bk.H3 + b3 + 1;
+  }
+  f4v acc[RB][2];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
+  const int S2 = bk.H3, S1 = bk.H2 * bk.H3, S0 = bk.H1 * S1;
+  if (!SPARSE_IN || p == 0)
+    nn_blk_taps<SPARSE_IN, 0, RB>(lds, W, rowpos, S0, S1, S2, lr, kc, ch, acc);
+  else
+    nn_blk_taps<SPARSE_IN, 1, RB>(lds, W, rowpos, S0, S1, S2, lr, kc, ch, acc);
+  __syncthreads();  // every wave is done with the halo: reuse LDS for the output tile
+
+  if (EPI == EPI_SPINOR) {
+    // even sites only: tile [256][24] FP32, then float4 stores per (component group, site)
+    float* st = reinterpret_cast<float*>(lds);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          int j = (g0 + rb * gstep) * 16 + (l >> 4) * 4 + i;
+          int c = cb * 16 + lr;
+          if (c < 24) st[j * 24 + c] = acc[rb][cb][i];
+        }
+    __syncthreads();
+    float scale = 1.0f, skc = 0.0f;
+    if (scal) scale = (float)sqrt(scal[i_s]);
+    if (rin) skc = scal2 ? (float)(skip / sqrt(scal2[i_s2])) : skip;
+    for (int idx = threadIdx.x; idx < 6 * (NN_BLK_SITES / 2); idx += 512) {
+      int j = idx % (NN_BLK_SITES / 2), slot = idx / (NN_BLK_SITES / 2);
+      int b0, b1, b2, b3;
+      nn_blk_site(bk, 0, j, b0, b1, b2, b3);
+      size_t o = (size_t)slot * g.Ve + geo_half(g, o0 + b0, o1 + b1, o2 + b2, o3 + b3);
+      float4 v = *reinterpret_cast<const float4*>(st + j * 24 + slot * 4);
+      v.x *= scale;
+      v.y *= scale;
+      v.z *= scale;
+      v.w *= scale;
+      if (rin) {
+        float4 r4 = reinterpret_cast<const float4*>(rin)[o];
+        v.x += skc * r4.x;
+        v.y += skc * r4.y;
+        v.z += skc * r4.z;
+        v.w += skc * r4.w;
+      }
+      reinterpret_cast<float4*>(out_f)[o] = v;
+    }
+  } else {
+    // tile [512][32] bf16 (site s = parity * 256 + j), then 16-byte stores
+    uint16_t* st = reinterpret_cast<uint16_t*>(lds);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          int s = p * (NN_BLK_SITES / 2) + (g0 + rb * gstep) * 16 + (l >> 4) * 4 + i;
+          float vv = acc[rb][cb][i];
+          st[s * NN_C + cb * 16 + lr] = f2bf(EPI == EPI_RELU ? fmaxf(vv, 0.f) : vv);
+        }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NN_BLK_SITES * 4; idx += 512) {
+      int s = idx >> 2, c = idx & 3;
+      int ps = s / (NN_BLK_SITES / 2), j = s % (NN_BLK_SITES / 2);
+      int b0, b1, b2, b3;
+      nn_blk_site(bk, ps, j, b0, b1, b2, b3);
+      size_t q = (size_t)ps * g.Ve + geo_half(g, o0 + b0, o1 + b1, o2 + b2, o3 + b3);
+      uint4 v = *reinterpret_cast<const uint4*>(st + s * NN_C + c * 8);
+      if (EPI == EPI_MASK) {
+        uint4 m = *reinterpret_cast<const uint4*>(mask + q * NN_C + c * 8);
+        uint32_t* vw = reinterpret_cast<uint32_t*>(&v);
+        const uint32_t* mw = reinterpret_cast<const uint32_t*>(&m);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          uint32_t keep = (bf16lo(mw[k]) > 0.f ? 0x0000ffffu : 0u) | (bf16hi(mw[k]) > 0.f ? 0xffff0000u : 0u);
+          vw[k] &= keep;
+        }
+      }
+      *reinterpret_cast<uint4*>(out_act + q * NN_C + c * 8) = v;
+    }
+  }
 }
 
 // layer-1 input: even sites carry r / |r| (channel 2c + 0/1 = Re/Im of
@@ -394,10 +659,42 @@ static qxd_status nn_repack(qxd_nn* net, hipStream_t s) {
 static void conv_launch(qxd_handle* h, int layer, const uint16_t* in, const uint16_t* W, int nout, int epi,
                         uint16_t* out_act, float* out_f, const uint16_t* mask, const double* scal, int i_s,
                         hipStream_t s, const float* rin = nullptr, float skip = 0.f, const double* scal2 = nullptr,
-                        int i_s2 = 0) {
+                        int i_s2 = 0, const qxd_nn* net = nullptr) {
+  const uint16_t* wl = W + (size_t)layer * NN_LAYER_W;
+  if (net && net->blk) {
+    NnBlk bk;
+    bk.B0 = net->bk[0];
+    bk.B1 = net->bk[1];
+    bk.B2 = net->bk[2];
+    bk.B3 = net->bk[3];
+    bk.H1 = bk.B1 + 2;
+    bk.H2 = bk.B2 + 2;
+    bk.H3 = bk.B3 + 2;
+    bk.npos = (bk.B0 + 2) * bk.H1 * bk.H2 * bk.H3;
+    bk.n1 = net->bk[4];
+    bk.n2 = net->bk[5];
+    bk.n3 = net->bk[6];
+    dim3 grid((unsigned)(h->V / NN_BLK_SITES)), blk(512);
+    // the layer-1 input and the layer-3 output gradient vanish on odd sites
+    if (epi == EPI_RELU && layer == 0)
+      hipLaunchKernelGGL((k_conv_blk<EPI_RELU, true, false>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
+                         mask, scal, i_s, rin, skip, scal2, i_s2);
+    else if (epi == EPI_RELU)
+      hipLaunchKernelGGL((k_conv_blk<EPI_RELU, false, false>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
+                         mask, scal, i_s, rin, skip, scal2, i_s2);
+    else if (epi == EPI_SPINOR)
+      hipLaunchKernelGGL((k_conv_blk<EPI_SPINOR, false, true>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
+                         mask, scal, i_s, rin, skip, scal2, i_s2);
+    else if (layer == 2)
+      hipLaunchKernelGGL((k_conv_blk<EPI_MASK, true, false>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
+                         mask, scal, i_s, rin, skip, scal2, i_s2);
+    else
+      hipLaunchKernelGGL((k_conv_blk<EPI_MASK, false, false>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
+                         mask, scal, i_s, rin, skip, scal2, i_s2);
+    return;
+  }
   int waves = div_up(nout, 64);
   dim3 grid(div_up(waves, 4));
-  const uint16_t* wl = W + (size_t)layer * NN_LAYER_W;
   if (epi == EPI_RELU) {
     if (layer == 0)
       hipLaunchKernelGGL((k_conv<EPI_RELU, true>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
@@ -412,6 +709,36 @@ static void conv_launch(qxd_handle* h, int layer, const uint16_t* in, const uint
     hipLaunchKernelGGL((k_conv<EPI_MASK, false>), grid, dim3(256), 0, s, h->geo, in, wl, nout, out_act, out_f, mask,
                        scal, i_s, rin, skip, scal2, i_s2);
   }
+}
+
+// Block shape of the tiled convolution: 512 sites, every extent even and
+// dividing the lattice extent, smallest halo that fits the LDS array (ties:
+// the longest x3 extent, which keeps the stores contiguous).  False when the
+// lattice admits none (the per-site gather kernel is used then).
+static bool nn_pick_blocks(const Geo& g, int* bk) {
+  const int ext[4] = {g.Le0, g.Le1, g.Le2, g.Le3};
+  const int cand[5] = {2, 4, 8, 16, 32};
+  int best = -1;
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b)
+      for (int c = 0; c < 5; ++c)
+        for (int d = 0; d < 5; ++d) {
+          int B[4] = {cand[a], cand[b], cand[c], cand[d]};
+          if (B[0] * B[1] * B[2] * B[3] != NN_BLK_SITES) continue;
+          bool ok = true;
+          for (int m = 0; m < 4; ++m) ok = ok && ext[m] % B[m] == 0;
+          int npos = (B[0] + 2) * (B[1] + 2) * (B[2] + 2) * (B[3] + 2);
+          if (!ok || npos > NN_HALO_MAX) continue;
+          if (best < 0 || npos < best || (npos == best && B[3] > bk[3])) {
+            best = npos;
+            for (int m = 0; m < 4; ++m) bk[m] = B[m];
+          }
+        }
+  if (best < 0) return false;
+  bk[4] = g.Le1 / bk[1];
+  bk[5] = g.Le2 / bk[2];
+  bk[6] = g.Le3 / bk[3];
+  return true;
 }
 
 static qxd_status nn_alloc_act(qxd_nn* net) {
@@ -448,11 +775,13 @@ static qxd_status nn_forward(qxd_handle* h, qxd_nn* net, const float4* r, float*
   if (with_norm) blas_norm2<float4>(h, r, (size_t)6 * h->Ve, h->scal + S_NN, s);
   hipLaunchKernelGGL(k_nn_embed, dim3(div_up(2 * h->Ve, 256)), dim3(256), 0, s, h->geo, r,
                      with_norm ? h->scal : nullptr, S_NN, net->a0);
-  conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s);
-  conv_launch(h, 1, net->a1, net->wf, (int)h->V, EPI_RELU, net->a2, nullptr, nullptr, nullptr, 0, s);
+  conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s, nullptr, 0.f,
+              nullptr, 0, net);
+  conv_launch(h, 1, net->a1, net->wf, (int)h->V, EPI_RELU, net->a2, nullptr, nullptr, nullptr, 0, s, nullptr, 0.f,
+              nullptr, 0, net);
   conv_launch(h, 2, net->a2, net->wf, (int)h->Ve, EPI_SPINOR, nullptr, out, nullptr, with_norm ? h->scal : nullptr,
               S_NN, s, net->skip != 0.f ? reinterpret_cast<const float*>(r) : nullptr, net->skip,
-              with_norm ? nullptr : h->scal, S_NN);
+              with_norm ? nullptr : h->scal, S_NN, net);
   QXD_HIP(hipGetLastError());
   return QXD_OK;
 }
@@ -473,10 +802,12 @@ static qxd_status nn_pair(qxd_handle* h, qxd_nn* net, const float4* r, const flo
   blas_norm2<float4>(h, e, nw, h->scal + slot + 1, s);
   // forward on r / |r| (scale 1 at the output): y = N(rhat)
   hipLaunchKernelGGL(k_nn_embed, dim3(div_up(2 * h->Ve, 256)), dim3(256), 0, s, h->geo, r, h->scal, slot, net->a0);
-  conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s);
-  conv_launch(h, 1, net->a1, net->wf, (int)h->V, EPI_RELU, net->a2, nullptr, nullptr, nullptr, 0, s);
+  conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s, nullptr, 0.f,
+              nullptr, 0, net);
+  conv_launch(h, 1, net->a1, net->wf, (int)h->V, EPI_RELU, net->a2, nullptr, nullptr, nullptr, 0, s, nullptr, 0.f,
+              nullptr, 0, net);
   conv_launch(h, 2, net->a2, net->wf, (int)h->Ve, EPI_SPINOR, nullptr, net->y, nullptr, nullptr, 0, s,
-              net->skip != 0.f ? reinterpret_cast<const float*>(r) : nullptr, net->skip, h->scal, slot);
+              net->skip != 0.f ? reinterpret_cast<const float*>(r) : nullptr, net->skip, h->scal, slot, net);
   // output gradient and loss partials
   int G = div_up(h->Ve, 256);
   if (kind == 0) {
@@ -501,12 +832,14 @@ static qxd_status nn_pair(qxd_handle* h, qxd_nn* net, const float4* r, const flo
   hipLaunchKernelGGL(k_conv_wgrad, wg_e, dim3(256), 0, s, h->geo, net->g3, net->a2, (int)h->Ve, kWgChunk, net->part);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(div_up(NN_TAPS * 24 * 32, 256)), dim3(256), 0, s, net->part,
                      (int)wg_e.x, 32, 24, kOff[2], net->grad);
-  conv_launch(h, 2, net->g3, net->wa, (int)h->V, EPI_MASK, net->gA, nullptr, net->a2, nullptr, 0, s);
+  conv_launch(h, 2, net->g3, net->wa, (int)h->V, EPI_MASK, net->gA, nullptr, net->a2, nullptr, 0, s, nullptr, 0.f,
+              nullptr, 0, net);
   // layer 2
   hipLaunchKernelGGL(k_conv_wgrad, wg, dim3(256), 0, s, h->geo, net->gA, net->a1, (int)h->V, kWgChunk, net->part);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(div_up(NN_TAPS * 32 * 32, 256)), dim3(256), 0, s, net->part, net->nchunk,
                      32, 32, kOff[1], net->grad);
-  conv_launch(h, 1, net->gA, net->wa, (int)h->V, EPI_MASK, net->gB, nullptr, net->a1, nullptr, 0, s);
+  conv_launch(h, 1, net->gA, net->wa, (int)h->V, EPI_MASK, net->gB, nullptr, net->a1, nullptr, 0, s, nullptr, 0.f,
+              nullptr, 0, net);
   // layer 1
   hipLaunchKernelGGL(k_conv_wgrad, wg, dim3(256), 0, s, h->geo, net->gB, net->a0, (int)h->V, kWgChunk, net->part);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(div_up(NN_TAPS * 32 * 24, 256)), dim3(256), 0, s, net->part, net->nchunk,
@@ -525,6 +858,8 @@ extern "C" qxd_status qxd_nn_create(qxd_handle* h, qxd_nn** out) {
   qxd_nn* net = new (std::nothrow) qxd_nn();
   if (!net) return QXD_ENOMEM;
   net->h = h;
+  const char* gather = getenv("QXD_NN_GATHER");
+  net->blk = !(gather && gather[0] == '1') && nn_pick_blocks(h->geo, net->bk);
   size_t n = QXD_NN_NWEIGHTS;
   if (hipMalloc(&net->w, n * 4) != hipSuccess || hipMalloc(&net->m, n * 4) != hipSuccess ||
       hipMalloc(&net->v, n * 4) != hipSuccess || hipMalloc(&net->grad, n * 4) != hipSuccess ||

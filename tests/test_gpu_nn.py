@@ -6,6 +6,8 @@ matrix cores and stores bf16 activations, so a few 1e-3 of relative noise per
 layer remain: the bars are 2e-2 for outputs and losses, 6e-2 for gradients, in
 norm).  Training, the preconditioned solve and the fallbacks are checked on the
 FP64 true residual."""
+import os
+
 import numpy as np
 import pytest
 
@@ -51,20 +53,37 @@ def from_half32(lat, o, t):
     return lat.unpack(full, qxd.F32).cpu().numpy()
 
 
-@pytest.fixture(scope="module", params=[((4, 2, 4, 4), 3), ((2, 4, 2, 6), 2), ((8, 4, 4, 4), 1)],
-                ids=["cs3", "cs2_ragged", "c0"])
+# Lattices of 512 sites or more whose extents admit 512-site blocks run the
+# block-tiled convolution; the others (and "gather") the per-site kernel.
+@pytest.fixture(scope="module", params=[((4, 2, 4, 4), 3, False), ((2, 4, 2, 6), 2, False), ((8, 4, 4, 4), 1, False),
+                                        ((8, 4, 4, 4), 1, True), ((4, 4, 4, 8), 3, False), ((8, 2, 4, 4), 2, False)],
+                ids=["cs3", "cs2_ragged", "c0", "c0_gather", "cs3_blocks", "cs2_one_block"])
 def lat_pair(request):
-    L, cstar = request.param
+    L, cstar, gather = request.param
     o, lat, _ = make_pair(L, cstar, FD, sigma=0.2, su1=0.3, seed=31)
+    lat.gather = gather
     yield o, lat
     lat.close()
+
+
+def new_net(lat):
+    """A network on `lat`; the per-site gather kernel when the lattice asks for it."""
+    old = os.environ.get("QXD_NN_GATHER")
+    os.environ["QXD_NN_GATHER"] = "1" if getattr(lat, "gather", False) else "0"
+    try:
+        return qxd.qxd_nn_create(lat.h)
+    finally:
+        if old is None:
+            del os.environ["QXD_NN_GATHER"]
+        else:
+            os.environ["QXD_NN_GATHER"] = old
 
 
 @pytest.mark.parametrize("skip", [0.0, 0.27])
 def test_forward_matches_oracle(lat_pair, skip):
     o, lat = lat_pair
     ws = init_weights(5)
-    net = qxd.qxd_nn_create(lat.h)
+    net = new_net(lat)
     qxd.qxd_nn_set_weights(net, flat(ws))
     qxd.qxd_nn_set_skip(net, skip)
     r = sg.spinor(41, o.V)
@@ -89,7 +108,7 @@ def test_forward_matches_oracle(lat_pair, skip):
 def test_loss_and_gradient_match_oracle(lat_pair, kind, skip):
     o, lat = lat_pair
     ws = init_weights(6, scale=1.5)
-    net = qxd.qxd_nn_create(lat.h)
+    net = new_net(lat)
     qxd.qxd_nn_set_weights(net, flat(ws))
     qxd.qxd_nn_set_skip(net, skip)
     par = o.parity()
@@ -119,9 +138,32 @@ def test_loss_and_gradient_match_oracle(lat_pair, kind, skip):
     qxd.qxd_nn_destroy(net)
 
 
+def test_block_and_gather_kernels_agree():
+    """The block-tiled and the per-site convolutions compute the same network
+    (up to FP32 summation order and the bf16 roundings it can flip)."""
+    o, lat, _ = make_pair((4, 4, 4, 8), 3, FD, sigma=0.2, su1=0.3, seed=32)
+    ws = flat(init_weights(7))
+    r = sg.spinor(43, o.V)
+    r[o.parity() == 1] = 0
+    outs = []
+    for gather in (False, True):
+        lat.gather = gather
+        net = new_net(lat)
+        qxd.qxd_nn_set_weights(net, ws)
+        qxd.qxd_nn_set_skip(net, 0.1)
+        out = lat.field(qxd.F32)
+        qxd.qxd_nn_apply(lat.h, net, out, half32(lat, o, r))
+        outs.append(out.cpu().double())
+        qxd.qxd_nn_destroy(net)
+    err = float(torch.linalg.norm(outs[0] - outs[1]) / torch.linalg.norm(outs[1]))
+    print("block vs gather rel diff %.2e" % err)
+    assert err < 5e-3
+    lat.close()
+
+
 def test_zero_weights_fall_back_and_still_converge(lat_pair):
     o, lat = lat_pair
-    net = qxd.qxd_nn_create(lat.h)
+    net = new_net(lat)
     qxd.qxd_nn_set_weights(net, np.zeros(qxd.NN_NWEIGHTS, np.float32))
     b = sg.spinor(70, o.V)
     x = lat.field(qxd.F64, full=True)
@@ -134,7 +176,7 @@ def test_zero_weights_fall_back_and_still_converge(lat_pair):
 
 def test_nan_weights_fall_back_and_still_converge(lat_pair):
     o, lat = lat_pair
-    net = qxd.qxd_nn_create(lat.h)
+    net = new_net(lat)
     w = flat(init_weights(7))
     w[100] = np.nan
     qxd.qxd_nn_set_weights(net, w)
