@@ -286,7 +286,7 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs):
                 info["loss_history"][-1]))
         bd = lat.pack(torch.from_numpy(b).cuda())
         x = lat.field(qxd.F64, full=True)
-        legs = [("cg_f64", lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, check_every=8), x, bd,
+        legs = [("cg_f64", lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F64, check_every=8), x, bd,
                                                      check=False)),
                 ("fgcr_f32_in_f64", lambda: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10,
                                                                                         inner_prec=qxd.F32),

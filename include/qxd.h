@@ -96,9 +96,9 @@ typedef enum { QXD_PRECOND_NONE = 0, QXD_PRECOND_NN = 1 } qxd_precond_kind;
 typedef struct {
   int nmx;             /* iteration limit (CG: iterations; FGCR: inner steps in total) */
   double res;          /* target true relative residual |b - D x| / |b| (full lattice) */
-  int inner_prec;      /* qxd_prec of the inner FGCR operator (F64: no defect correction) */
+  int inner_prec;      /* qxd_prec of the inner CG / FGCR operator (F64: no defect correction) */
   double inner_res;    /* relative residual reduction asked of each inner solve */
-  int nkv;             /* FGCR restart length (1..64) */
+  int nkv;             /* FGCR restart length (1..24; 0: 16) */
   int max_outer;       /* defect-correction steps limit */
   int check_every;     /* CG: read the residual back every this many iterations */
   int fallback_after;  /* NN FGCR: inner steps without progress before dropping M */
@@ -174,9 +174,13 @@ qxd_status qxd_pack(qxd_handle *h, qxd_prec p, void *soa, const double *aos, voi
 qxd_status qxd_unpack(qxd_handle *h, qxd_prec p, double *aos, const void *soa, void *stream);
 
 /* Solve D x = b to |b - D x| / |b| <= params->res by CG on the normal equations
- * of the Schur system, all in FP64 (Sec. 4.4): source preparation, CG, and
- * reconstruction; the residual is recomputed in FP64 on the full lattice before
- * returning.  b, x: F64 full fields (device).  stats may be NULL. */
+ * of the Schur system (Sec. 4.4): source preparation, CG, and reconstruction;
+ * the residual is recomputed in FP64 on the full lattice before returning.
+ * inner_prec F64: CG in FP64.  F32 or BF16: an FP64 defect-correction loop
+ * (r = bhat - D_hat x in FP64, x += |r| e) around an inner CG on the normal
+ * equations whose operator and vectors are FP32 (BF16: links and spinors stored
+ * in bfloat16), run to the relative residual max(inner_res, res |b| / (2 |r|)).
+ * b, x: F64 full fields (device).  stats may be NULL. */
 qxd_status qxd_solve_cg(qxd_handle *h, const qxd_solver_params *params, void *x, const void *b,
                         qxd_solver_stats *stats, void *stream);
 

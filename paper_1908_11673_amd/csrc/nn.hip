@@ -53,7 +53,7 @@ struct qxd_nn {
   float* part = nullptr;   // weight-gradient partials
   int nchunk = 0;
   bool blk = false;        // block-tiled convolutions (else per-site gathers)
-  int bk[7] = {0, 0, 0, 0, 0, 0, 0};  // B0..B3, n1..n3 of the block tiling
+  int ncu = 1;             // compute units: workgroups of the persistent convolution
 };
 
 static const int kWgChunk = 2048;  // sites per weight-gradient workgroup
@@ -192,39 +192,57 @@ __global__ __launch_bounds__(256) void k_conv(Geo g, const uint16_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Block-tiled convolution.  A workgroup of 8 waves owns a B0 x B1 x B2 x B3
-// block of 512 sites (every B even, dividing the extended extents, so the
+// Block-tiled convolution.  The lattice is cut into B0 x B1 x B2 x B3 blocks
+// of 512 sites (every B even and dividing the extended extent, so the
 // block origin is an even site and local parity equals lattice parity).  The
-// block and its one-site halo are staged once in LDS (64 bytes per site, the
-// four 16-byte chunks XOR-swizzled against LDS bank conflicts), every tap then
-// reads its MFMA operands from LDS at a constant offset: with the 3^4 stencil
-// each activation is fetched from memory about (B+2)^4 / B^4 ~ 4 times instead
-// of 81 times.  The halo follows the C* neighbour map (a crossing of the k <=
-// cstar boundaries moves x1 by L1; two crossings cancel).  Rows of one MFMA
-// tile share a parity, so with an input that vanishes on odd sites (SPARSE_IN)
-// the taps landing on odd sites are skipped for whole waves, and odd halo sites
-// are not loaded.  EVEN_OUT computes the even sites only (last layer).
-struct NnBlk {
-  int B0, B1, B2, B3;  // block extents
-  int H1, H2, H3;      // halo extents B + 2 (H0 = B0 + 2)
-  int npos;            // halo positions
-  int n1, n2, n3;      // blocks along directions 1..3
+// block and its one-site halo are staged once in LDS, 64 bytes per site, so
+// with the 3^4 stencil each activation is fetched from memory about
+// (B+2)^4 / B^4 ~ 4 times instead of 81 times.  The halo follows the C*
+// neighbour map (a crossing of a k <= cstar boundary moves x1 by L1; two
+// crossings cancel).  Rows of one MFMA tile share a parity, so with an input
+// that vanishes on odd sites (SPARSE_IN) the taps landing on odd sites are
+// skipped for whole waves and odd halo sites are not loaded.  EVEN_OUT
+// computes the even sites only (last layer).
+//
+// LDS layout: halo coordinates h = b + 1 in [0, B + 2); site (h0, h1, h2, h3)
+// at byte h0 T0 + h1 T1 + h2 T2 + 64 h3, its four 16-byte channel chunks
+// XOR-swizzled by (h3 / 2) mod 4 against bank conflicts (rows of a tile are
+// same-parity sites two apart along x3).  The address is linear in h0..h2 and
+// the swizzle depends on h3 only, so each lane keeps three row addresses (one
+// per d3) and every tap reads its operands at a compile-time offset.
+template <int B0_, int B1_, int B2_, int B3_>
+struct NnShape {
+  static constexpr int B0 = B0_, B1 = B1_, B2 = B2_, B3 = B3_;
+  static constexpr int H0 = B0 + 2, H1 = B1 + 2, H2 = B2 + 2, H3 = B3 + 2;
+  static constexpr int NPOS = H0 * H1 * H2 * H3;
+  static constexpr int T2 = 64 * H3, T1 = T2 * H2, T0 = T1 * H1;
+  static constexpr int LDS_BYTES = (NPOS + 127) / 128 * 128 * 64;  // halo rounded up to 128 positions
+  static_assert(B0 * B1 * B2 * B3 == 512, "blocks of 512 sites");
+  static_assert(B0 % 2 == 0 && B1 % 2 == 0 && B2 % 2 == 0 && B3 % 2 == 0, "even block extents");
+  static_assert(LDS_BYTES <= 163840, "halo exceeds the LDS");
+  static_assert(2 * (T0 + T1 + T2) < 65536, "tap offsets exceed the LDS immediate");
 };
 
 #define NN_BLK_SITES 512
-#define NN_HALO_MAX 2400  // largest halo admitted (153600 bytes)
-#define NN_LDS_POS 2560   // LDS positions: 5 per thread, 163840 bytes
+// t x x1 x x2 x x3 extents of the blocks: the x3 extent 8 keeps four
+// same-parity sites (256 contiguous bytes of activations) per x3 line
+typedef NnShape<4, 4, 4, 8> NnBlock;
 
-__device__ inline int nn_lds_off(int pos, int c) { return pos * 64 + ((c ^ ((pos >> 1) & 3)) << 4); }
+// byte address of chunk c of halo site h (see the layout above)
+template <class SH>
+__device__ __forceinline__ int nn_lds_addr(int h0, int h1, int h2, int h3, int c) {
+  return h0 * SH::T0 + h1 * SH::T1 + h2 * SH::T2 + 64 * h3 + ((c ^ ((h3 >> 1) & 3)) << 4);
+}
 
 // j-th site of parity p inside the block: local coordinates
-__device__ inline void nn_blk_site(const NnBlk& bk, int p, int j, int& b0, int& b1, int& b2, int& b3) {
-  int r3 = bk.B3 >> 1;
+template <class SH>
+__device__ __forceinline__ void nn_blk_site(int p, int j, int& b0, int& b1, int& b2, int& b3) {
+  constexpr int r3 = SH::B3 / 2;
   int k = j % r3, line = j / r3;
-  b2 = line % bk.B2;
-  line /= bk.B2;
-  b1 = line % bk.B1;
-  b0 = line / bk.B1;
+  b2 = line % SH::B2;
+  line /= SH::B2;
+  b1 = line % SH::B1;
+  b0 = line / SH::B1;
   b3 = 2 * k + ((b0 + b1 + b2 + p) & 1);
 }
 
@@ -242,32 +260,34 @@ struct NnTapList {
   }
 };
 
-// The tap loop of the block kernel, fully unrolled: the weights of tap k + NN_WPF
-// are requested while tap k is contracted, and the LDS operands of tap k + 1
-// are read before the matrix-core instructions of tap k, so neither the L2
-// latency of the weights nor the LDS latency stalls the waves.
+// The tap loop, fully unrolled: the weights of tap k + NN_WPF are requested
+// while tap k is contracted, and the LDS operands of tap k + 1 are read before
+// the matrix-core instructions of tap k.  raddr[rb][d3 + 1] is the byte
+// address of row rb's neighbour at (-1, -1, -1, d3); tap (d0, d1, d2, d3)
+// adds the constant (d0 + 1) T0 + (d1 + 1) T1 + (d2 + 1) T2.
 #define NN_WPF 8
-template <bool SPARSE, int P, int RB>
-__device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __restrict__ W, const int* rowpos, int S0,
-                                            int S1, int S2, int lr, int kc, int ch, f4v (&acc)[RB][2]) {
+#ifndef NN_WAVES
+#define NN_WAVES 8  // waves per workgroup of the block kernel
+#endif
+template <class SH, bool SPARSE, int P, int RB>
+__device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __restrict__ W, const int (&raddr)[RB][3],
+                                            int lr, int kc, f4v (&acc)[RB][2]) {
   constexpr NnTapList<SPARSE, P> TL{};
-  auto tap_off = [&](int tap) {
-    return (tap / 27 - 1) * S0 + (tap / 9 % 3 - 1) * S1 + (tap / 3 % 3 - 1) * S2 + (tap % 3 - 1);
-  };
+  static_assert(TL.n > NN_WPF, "weight prefetch deeper than the tap list");
   bf16x8 wb[NN_WPF][2];
 #pragma unroll
-  for (int k = 0; k < NN_WPF; ++k)
-    if (k < TL.n) {
-      const uint16_t* wt = W + TL.t[k] * (NN_C * NN_C);
-      wb[k][0] = ld8(wt + lr * NN_C + kc);
-      wb[k][1] = ld8(wt + (16 + lr) * NN_C + kc);
-    }
-  bf16x8 a[RB];
-  {
-    int off = tap_off(TL.t[0]);
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) a[rb] = *reinterpret_cast<const bf16x8*>(lds + nn_lds_off(rowpos[rb] + off, ch));
+  for (int k = 0; k < NN_WPF; ++k) {
+    const uint16_t* wt = W + TL.t[k] * (NN_C * NN_C);
+    wb[k][0] = ld8(wt + lr * NN_C + kc);
+    wb[k][1] = ld8(wt + (16 + lr) * NN_C + kc);
   }
+  auto rd = [&](int rb, int tap) {
+    const int off = (tap / 27) * SH::T0 + (tap / 9 % 3) * SH::T1 + (tap / 3 % 3) * SH::T2;
+    return *reinterpret_cast<const bf16x8*>(lds + raddr[rb][tap % 3] + off);
+  };
+  bf16x8 a[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) a[rb] = rd(rb, TL.t[0]);
 #pragma unroll
   for (int k = 0; k < TL.n; ++k) {
     bf16x8 w0 = wb[k % NN_WPF][0], w1 = wb[k % NN_WPF][1];
@@ -278,10 +298,8 @@ __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __r
     }
     bf16x8 an[RB];
     if (k + 1 < TL.n) {
-      int off = tap_off(TL.t[k + 1]);
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-        an[rb] = *reinterpret_cast<const bf16x8*>(lds + nn_lds_off(rowpos[rb] + off, ch));
+      for (int rb = 0; rb < RB; ++rb) an[rb] = rd(rb, TL.t[k + 1]);
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
@@ -295,161 +313,206 @@ __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __r
   }
 }
 
-template <int EPI, bool SPARSE_IN, bool EVEN_OUT>
-__global__ __launch_bounds__(512) void k_conv_blk(Geo g, NnBlk bk, const uint16_t* __restrict__ in,
-                                                  const uint16_t* __restrict__ W, uint16_t* __restrict__ out_act,
-                                                  float* __restrict__ out_f, const uint16_t* __restrict__ mask,
-                                                  const double* __restrict__ scal, int i_s,
-                                                  const float* __restrict__ rin, float skip,
-                                                  const double* __restrict__ scal2, int i_s2) {
-  __shared__ uint4 lds4[NN_LDS_POS * 4];
-  char* lds = reinterpret_cast<char*>(lds4);
-  const int b = site_tile(blockIdx.x, gridDim.x, -1);
-  int c3 = b % bk.n3, t = b / bk.n3;
-  int c2 = t % bk.n2;
-  t /= bk.n2;
-  int c1 = t % bk.n1, c0 = t / bk.n1;
-  const int o0 = c0 * bk.B0, o1 = c1 * bk.B1, o2 = c2 * bk.B2, o3 = c3 * bk.B3;
-
-  // stage block + halo: one thread per halo position, 64 bytes each; every
-  // load of the thread is issued before the first LDS write
-  // Four consecutive threads move the four 16-byte chunks of one position, so a
-  // wave-wide load covers 16 whole sites; each thread issues all its loads
-  // before its first LDS write.  Positions past the halo and skipped odd sites
-  // are filled with the first site (never read).
-  constexpr int PPT = NN_LDS_POS / 128;
-  static_assert(NN_LDS_POS >= NN_HALO_MAX, "halo staging");
+// Halo of the block with origin o, staged through registers in two halves:
+// this thread moves chunk threadIdx & 3 of the positions threadIdx / 4 + 64 k.
+// Positions past the halo and skipped odd sites read the first site; they are
+// written to LDS but never read.  Every load of a half is issued before its
+// first LDS write.
+template <class SH, int NW, bool SPARSE_IN>
+__device__ __forceinline__ void nn_halo_stage(const Geo& g, const uint16_t* __restrict__ in, char* lds, int o0,
+                                              int o1, int o2, int o3) {
+  constexpr int GRP = 16 * NW;                       // positions per pass of the workgroup
+  constexpr int HPT = (SH::NPOS + GRP - 1) / GRP;    // positions per thread
+  static_assert(HPT * GRP * 64 <= SH::LDS_BYTES, "halo staging");
+  constexpr int HALF = NW >= 8 ? HPT : (HPT + 1) / 2;
   const int hc = threadIdx.x & 3;
-  // integer division by the small halo extents through a float reciprocal:
-  // (n + 1/2) / H stays at least 1/(2H) away from an integer for n < 2^12
-  const float rH1 = 1.0f / bk.H1, rH2 = 1.0f / bk.H2, rH3 = 1.0f / bk.H3;
-  uint4 hv[PPT];
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    int pos = (threadIdx.x >> 2) + 128 * k;
-    bool ok = pos < bk.npos;
-    int r = (int)(((float)pos + 0.5f) * rH3);
-    int h3 = pos - r * bk.H3;
-    int r2 = (int)(((float)r + 0.5f) * rH2);
-    int h2 = r - r2 * bk.H2;
-    int h0 = (int)(((float)r2 + 0.5f) * rH1);
-    int h1 = r2 - h0 * bk.H1;
-    int x0 = o0 + h0 - 1, x1 = o1 + h1 - 1, x2 = o2 + h2 - 1, x3 = o3 + h3 - 1;
-    x0 = x0 < 0 ? x0 + g.Le0 : (x0 >= g.Le0 ? x0 - g.Le0 : x0);
-    x1 = x1 < 0 ? x1 + g.Le1 : (x1 >= g.Le1 ? x1 - g.Le1 : x1);
-    bool mir = false;
-    if (x2 < 0 || x2 >= g.Le2) {
-      x2 = x2 < 0 ? x2 + g.Le2 : x2 - g.Le2;
-      mir = g.cstar >= 2;
+  for (int k0 = 0; k0 < HPT; k0 += HALF) {
+    uint4 hv[HALF];
+#pragma unroll
+    for (int k = 0; k < HALF; ++k) {
+      int pos = (threadIdx.x >> 2) + GRP * (k0 + k);
+      bool ok = pos < SH::NPOS;
+      int h3 = pos % SH::H3, r = pos / SH::H3;
+      int h2 = r % SH::H2;
+      r /= SH::H2;
+      int h1 = r % SH::H1, h0 = r / SH::H1;
+      int x0 = o0 + h0 - 1, x1 = o1 + h1 - 1, x2 = o2 + h2 - 1, x3 = o3 + h3 - 1;
+      x0 = x0 < 0 ? x0 + g.Le0 : (x0 >= g.Le0 ? x0 - g.Le0 : x0);
+      x1 = x1 < 0 ? x1 + g.Le1 : (x1 >= g.Le1 ? x1 - g.Le1 : x1);
+      bool mir = false;
+      if (x2 < 0 || x2 >= g.Le2) {
+        x2 = x2 < 0 ? x2 + g.Le2 : x2 - g.Le2;
+        mir = g.cstar >= 2;
+      }
+      if (x3 < 0 || x3 >= g.Le3) {
+        x3 = x3 < 0 ? x3 + g.Le3 : x3 - g.Le3;
+        if (g.cstar >= 3) mir = !mir;
+      }
+      if (mir) x1 = geo_mirror_x1(g, x1);
+      int par = (x0 + x1 + x2 + x3) & 1;
+      ok = ok && !(SPARSE_IN && par) && k0 + k < HPT;
+      size_t q = ok ? (size_t)par * g.Ve + geo_half(g, x0, x1, x2, x3) : 0;
+      hv[k] = reinterpret_cast<const uint4*>(in + q * NN_C)[hc];
     }
-    if (x3 < 0 || x3 >= g.Le3) {
-      x3 = x3 < 0 ? x3 + g.Le3 : x3 - g.Le3;
-      if (g.cstar >= 3) mir = !mir;
+#pragma unroll
+    for (int k = 0; k < HALF; ++k) {
+      if (k0 + k >= HPT) break;
+      int pos = (threadIdx.x >> 2) + GRP * (k0 + k);
+      int h3 = pos % SH::H3;
+      *reinterpret_cast<uint4*>(lds + pos * 64 + ((hc ^ ((h3 >> 1) & 3)) << 4)) = hv[k];
     }
-    if (mir) x1 = geo_mirror_x1(g, x1);
-    int par = (x0 + x1 + x2 + x3) & 1;
-    ok = ok && !(SPARSE_IN && par);
-    size_t q = ok ? (size_t)par * g.Ve + geo_half(g, x0, x1, x2, x3) : 0;
-    hv[k] = reinterpret_cast<const uint4*>(in + q * NN_C)[hc];
   }
-#pragma unroll
-  for (int k = 0; k < PPT; ++k)
-    *reinterpret_cast<uint4*>(lds + nn_lds_off((threadIdx.x >> 2) + 128 * k, hc)) = hv[k];
-  __syncthreads();
+}
 
-  constexpr int RB = EVEN_OUT ? 2 : 4;
+// Persistent block-tiled convolution: a workgroup of 4 waves (one per SIMD)
+// walks blocks, and the workgroups of one XCD walk one contiguous eighth of the
+// block list together, so neighbouring blocks share that XCD's L2.  A wave owns
+// 8 row tiles of 16 same-parity sites (128 sites; the last layer: 4 tiles of
+// even sites) and all 32 output channels, so each weight tile it loads feeds
+// 16 matrix-core instructions.  Per block: halo to LDS, taps, output tile
+// staged in LDS, coalesced stores.
+template <int NW, int EPI, bool SPARSE_IN, bool EVEN_OUT>
+__global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint16_t* __restrict__ in,
+                                                 const uint16_t* __restrict__ W, uint16_t* __restrict__ out_act,
+                                                 float* __restrict__ out_f, const uint16_t* __restrict__ mask,
+                                                 const double* __restrict__ scal, int i_s,
+                                                 const float* __restrict__ rin, float skip,
+                                                 const double* __restrict__ scal2, int i_s2) {
+  using SH = NnBlock;
+  __shared__ uint4 lds4[SH::LDS_BYTES / 16];
+  char* lds = reinterpret_cast<char*>(lds4);
+  const int n1 = g.Le1 / SH::B1, n2 = g.Le2 / SH::B2, n3 = g.Le3 / SH::B3;
+  // this workgroup's blocks: group x = blockIdx % nx (the XCD when nx = 8) owns
+  // blocks [x per, (x + 1) per), walked by its nwx workgroups in turn
+  const int nx = min(8, (int)gridDim.x);
+  const int xcd = blockIdx.x % nx, wi = blockIdx.x / nx;
+  const int nwx = ((int)gridDim.x - xcd + nx - 1) / nx;
+  const int per = (nblk + nx - 1) / nx;
+  const int bbeg = min(nblk, xcd * per), bend = min(nblk, (xcd + 1) * per);
+  auto origin = [&](int b, int& o0, int& o1, int& o2, int& o3) {
+    int c3 = b % n3, t = b / n3;
+    int c2 = t % n2;
+    t /= n2;
+    int c1 = t % n1, c0 = t / n1;
+    o0 = c0 * SH::B0;
+    o1 = c1 * SH::B1;
+    o2 = c2 * SH::B2;
+    o3 = c3 * SH::B3;
+  };
+
+  // NW waves share the 32 row tiles (16 of each parity; 16 even ones only with EVEN_OUT)
+  constexpr int RB = (EVEN_OUT ? 16 : 32) / NW;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int lr = l & 15, kc = (l >> 4) * 8, ch = l >> 4;
-  const int p = EVEN_OUT ? 0 : (wave >> 2);
-  const int g0 = EVEN_OUT ? wave : (wave & 3), gstep = EVEN_OUT ? 8 : 4;
-  int rowpos[RB];
+  const int p = EVEN_OUT ? 0 : wave / (NW / 2);
+  const int g0 = EVEN_OUT ? wave : wave % (NW / 2), gstep = EVEN_OUT ? NW : NW / 2;
+  int raddr[RB][3];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     int b0, b1, b2, b3;
-    nn_blk_site(bk, p, (g0 + rb * gstep) * 16 + lr, b0, b1, b2, b3);
-    rowpos[rb] = (((b0 + 1) * bk.H1 + b1 + 1) * bk.H2 + b2 + 1) * bk.H3 + b3 + 1;
+    nn_blk_site<SH>(p, (g0 + rb * gstep) * 16 + lr, b0, b1, b2, b3);
+#pragma unroll
+    for (int d3 = 0; d3 < 3; ++d3) raddr[rb][d3] = nn_lds_addr<SH>(b0, b1, b2, b3 + d3, ch);
   }
-  f4v acc[RB][2];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
-  const int S2 = bk.H3, S1 = bk.H2 * bk.H3, S0 = bk.H1 * S1;
-  if (!SPARSE_IN || p == 0)
-    nn_blk_taps<SPARSE_IN, 0, RB>(lds, W, rowpos, S0, S1, S2, lr, kc, ch, acc);
-  else
-    nn_blk_taps<SPARSE_IN, 1, RB>(lds, W, rowpos, S0, S1, S2, lr, kc, ch, acc);
-  __syncthreads();  // every wave is done with the halo: reuse LDS for the output tile
-
+  float scale = 1.0f, skc = 0.0f;
   if (EPI == EPI_SPINOR) {
-    // even sites only: tile [256][24] FP32, then float4 stores per (component group, site)
-    float* st = reinterpret_cast<float*>(lds);
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          int j = (g0 + rb * gstep) * 16 + (l >> 4) * 4 + i;
-          int c = cb * 16 + lr;
-          if (c < 24) st[j * 24 + c] = acc[rb][cb][i];
-        }
-    __syncthreads();
-    float scale = 1.0f, skc = 0.0f;
     if (scal) scale = (float)sqrt(scal[i_s]);
     if (rin) skc = scal2 ? (float)(skip / sqrt(scal2[i_s2])) : skip;
-    for (int idx = threadIdx.x; idx < 6 * (NN_BLK_SITES / 2); idx += 512) {
-      int j = idx % (NN_BLK_SITES / 2), slot = idx / (NN_BLK_SITES / 2);
-      int b0, b1, b2, b3;
-      nn_blk_site(bk, 0, j, b0, b1, b2, b3);
-      size_t o = (size_t)slot * g.Ve + geo_half(g, o0 + b0, o1 + b1, o2 + b2, o3 + b3);
-      float4 v = *reinterpret_cast<const float4*>(st + j * 24 + slot * 4);
-      v.x *= scale;
-      v.y *= scale;
-      v.z *= scale;
-      v.w *= scale;
-      if (rin) {
-        float4 r4 = reinterpret_cast<const float4*>(rin)[o];
-        v.x += skc * r4.x;
-        v.y += skc * r4.y;
-        v.z += skc * r4.z;
-        v.w += skc * r4.w;
-      }
-      reinterpret_cast<float4*>(out_f)[o] = v;
-    }
-  } else {
-    // tile [512][32] bf16 (site s = parity * 256 + j), then 16-byte stores
-    uint16_t* st = reinterpret_cast<uint16_t*>(lds);
+  }
+
+  for (int b = bbeg + wi; b < bend; b += nwx) {
+    int o0, o1, o2, o3;
+    origin(b, o0, o1, o2, o3);
+    nn_halo_stage<SH, NW, SPARSE_IN>(g, in, lds, o0, o1, o2, o3);
+    __syncthreads();
+    f4v acc[RB][2];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
+    // the weight loads do not depend on the block: keep the compiler from
+    // hoisting all 81 taps' worth out of the block loop
+    const uint16_t* Wb = W;
+    asm volatile("" : "+s"(Wb));
+    if (!SPARSE_IN || p == 0)
+      nn_blk_taps<SH, SPARSE_IN, 0, RB>(lds, Wb, raddr, lr, kc, acc);
+    else
+      nn_blk_taps<SH, SPARSE_IN, 1, RB>(lds, Wb, raddr, lr, kc, acc);
+    __syncthreads();  // every wave is done with the halo: the LDS takes the output tile
+    const int hb = geo_half(g, o0, o1, o2, o3);
+    if (EPI == EPI_SPINOR) {
+      // even sites only: tile [256][24] FP32, then float4 stores per (component group, site)
+      float* st = reinterpret_cast<float*>(lds);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          int s = p * (NN_BLK_SITES / 2) + (g0 + rb * gstep) * 16 + (l >> 4) * 4 + i;
-          float vv = acc[rb][cb][i];
-          st[s * NN_C + cb * 16 + lr] = f2bf(EPI == EPI_RELU ? fmaxf(vv, 0.f) : vv);
-        }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < NN_BLK_SITES * 4; idx += 512) {
-      int s = idx >> 2, c = idx & 3;
-      int ps = s / (NN_BLK_SITES / 2), j = s % (NN_BLK_SITES / 2);
-      int b0, b1, b2, b3;
-      nn_blk_site(bk, ps, j, b0, b1, b2, b3);
-      size_t q = (size_t)ps * g.Ve + geo_half(g, o0 + b0, o1 + b1, o2 + b2, o3 + b3);
-      uint4 v = *reinterpret_cast<const uint4*>(st + s * NN_C + c * 8);
-      if (EPI == EPI_MASK) {
-        uint4 m = *reinterpret_cast<const uint4*>(mask + q * NN_C + c * 8);
-        uint32_t* vw = reinterpret_cast<uint32_t*>(&v);
-        const uint32_t* mw = reinterpret_cast<const uint32_t*>(&m);
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uint32_t keep = (bf16lo(mw[k]) > 0.f ? 0x0000ffffu : 0u) | (bf16hi(mw[k]) > 0.f ? 0xffff0000u : 0u);
-          vw[k] &= keep;
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            int j = (g0 + rb * gstep) * 16 + (l >> 4) * 4 + i;
+            int c = cb * 16 + lr;
+            if (c < 24) st[j * 24 + c] = acc[rb][cb][i];
+          }
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < 6 * 4 / NW; ++it) {
+        int idx = threadIdx.x + 64 * NW * it;
+        int j = idx % (NN_BLK_SITES / 2), slot = idx / (NN_BLK_SITES / 2);
+        int b0, b1, b2, b3;
+        nn_blk_site<SH>(0, j, b0, b1, b2, b3);
+        size_t o = (size_t)slot * g.Ve + hb + geo_half(g, b0, b1, b2, b3);
+        float4 v = *reinterpret_cast<const float4*>(st + j * 24 + slot * 4);
+        v.x *= scale;
+        v.y *= scale;
+        v.z *= scale;
+        v.w *= scale;
+        if (rin) {
+          float4 r4 = reinterpret_cast<const float4*>(rin)[o];
+          v.x += skc * r4.x;
+          v.y += skc * r4.y;
+          v.z += skc * r4.z;
+          v.w += skc * r4.w;
         }
+        reinterpret_cast<float4*>(out_f)[o] = v;
       }
-      *reinterpret_cast<uint4*>(out_act + q * NN_C + c * 8) = v;
+    } else {
+      // tile [512][32] bf16 (site s = parity * 256 + j), then 16-byte stores
+      uint16_t* st = reinterpret_cast<uint16_t*>(lds);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            int s = p * (NN_BLK_SITES / 2) + (g0 + rb * gstep) * 16 + (l >> 4) * 4 + i;
+            float vv = acc[rb][cb][i];
+            st[s * NN_C + cb * 16 + lr] = f2bf(EPI == EPI_RELU ? fmaxf(vv, 0.f) : vv);
+          }
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < 8 * 4 / NW; ++it) {
+        int idx = threadIdx.x + 64 * NW * it;
+        int s = idx >> 2, c = idx & 3;
+        int ps = s / (NN_BLK_SITES / 2), j = s % (NN_BLK_SITES / 2);
+        int b0, b1, b2, b3;
+        nn_blk_site<SH>(ps, j, b0, b1, b2, b3);
+        size_t q = (size_t)ps * g.Ve + hb + geo_half(g, b0, b1, b2, b3);
+        uint4 v = *reinterpret_cast<const uint4*>(st + s * NN_C + c * 8);
+        if (EPI == EPI_MASK) {
+          uint4 m = *reinterpret_cast<const uint4*>(mask + q * NN_C + c * 8);
+          uint32_t* vw = reinterpret_cast<uint32_t*>(&v);
+          const uint32_t* mw = reinterpret_cast<const uint32_t*>(&m);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            uint32_t keep = (bf16lo(mw[k]) > 0.f ? 0x0000ffffu : 0u) | (bf16hi(mw[k]) > 0.f ? 0xffff0000u : 0u);
+            vw[k] &= keep;
+          }
+        }
+        *reinterpret_cast<uint4*>(out_act + q * NN_C + c * 8) = v;
+      }
     }
+    __syncthreads();  // the output tile has left the LDS
   }
 }
 
@@ -656,41 +719,37 @@ static qxd_status nn_repack(qxd_nn* net, hipStream_t s) {
   return QXD_OK;
 }
 
+static void conv_launch_blk(qxd_handle* h, const qxd_nn* net, int layer, const uint16_t* in, const uint16_t* wl,
+                            int epi, uint16_t* out_act, float* out_f, const uint16_t* mask, const double* scal, int i_s,
+                            hipStream_t s, const float* rin, float skip, const double* scal2, int i_s2) {
+  const int nblk = (int)(h->V / NN_BLK_SITES);
+  constexpr int NW = NN_WAVES;
+  dim3 grid((unsigned)std::min(nblk, net->ncu)), blk(64 * NW);
+  // the layer-1 input and the layer-3 output gradient vanish on odd sites
+  if (epi == EPI_RELU && layer == 0)
+    hipLaunchKernelGGL((k_conv_ws<NW, EPI_RELU, true, false>), grid, blk, 0, s, h->geo, nblk, in, wl, out_act, out_f, mask,
+                       scal, i_s, rin, skip, scal2, i_s2);
+  else if (epi == EPI_RELU)
+    hipLaunchKernelGGL((k_conv_ws<NW, EPI_RELU, false, false>), grid, blk, 0, s, h->geo, nblk, in, wl, out_act, out_f,
+                       mask, scal, i_s, rin, skip, scal2, i_s2);
+  else if (epi == EPI_SPINOR)
+    hipLaunchKernelGGL((k_conv_ws<NW, EPI_SPINOR, false, true>), grid, blk, 0, s, h->geo, nblk, in, wl, out_act, out_f,
+                       mask, scal, i_s, rin, skip, scal2, i_s2);
+  else if (layer == 2)
+    hipLaunchKernelGGL((k_conv_ws<NW, EPI_MASK, true, false>), grid, blk, 0, s, h->geo, nblk, in, wl, out_act, out_f, mask,
+                       scal, i_s, rin, skip, scal2, i_s2);
+  else
+    hipLaunchKernelGGL((k_conv_ws<NW, EPI_MASK, false, false>), grid, blk, 0, s, h->geo, nblk, in, wl, out_act, out_f,
+                       mask, scal, i_s, rin, skip, scal2, i_s2);
+}
+
 static void conv_launch(qxd_handle* h, int layer, const uint16_t* in, const uint16_t* W, int nout, int epi,
                         uint16_t* out_act, float* out_f, const uint16_t* mask, const double* scal, int i_s,
                         hipStream_t s, const float* rin = nullptr, float skip = 0.f, const double* scal2 = nullptr,
                         int i_s2 = 0, const qxd_nn* net = nullptr) {
   const uint16_t* wl = W + (size_t)layer * NN_LAYER_W;
   if (net && net->blk) {
-    NnBlk bk;
-    bk.B0 = net->bk[0];
-    bk.B1 = net->bk[1];
-    bk.B2 = net->bk[2];
-    bk.B3 = net->bk[3];
-    bk.H1 = bk.B1 + 2;
-    bk.H2 = bk.B2 + 2;
-    bk.H3 = bk.B3 + 2;
-    bk.npos = (bk.B0 + 2) * bk.H1 * bk.H2 * bk.H3;
-    bk.n1 = net->bk[4];
-    bk.n2 = net->bk[5];
-    bk.n3 = net->bk[6];
-    dim3 grid((unsigned)(h->V / NN_BLK_SITES)), blk(512);
-    // the layer-1 input and the layer-3 output gradient vanish on odd sites
-    if (epi == EPI_RELU && layer == 0)
-      hipLaunchKernelGGL((k_conv_blk<EPI_RELU, true, false>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
-                         mask, scal, i_s, rin, skip, scal2, i_s2);
-    else if (epi == EPI_RELU)
-      hipLaunchKernelGGL((k_conv_blk<EPI_RELU, false, false>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
-                         mask, scal, i_s, rin, skip, scal2, i_s2);
-    else if (epi == EPI_SPINOR)
-      hipLaunchKernelGGL((k_conv_blk<EPI_SPINOR, false, true>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
-                         mask, scal, i_s, rin, skip, scal2, i_s2);
-    else if (layer == 2)
-      hipLaunchKernelGGL((k_conv_blk<EPI_MASK, true, false>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
-                         mask, scal, i_s, rin, skip, scal2, i_s2);
-    else
-      hipLaunchKernelGGL((k_conv_blk<EPI_MASK, false, false>), grid, blk, 0, s, h->geo, bk, in, wl, out_act, out_f,
-                         mask, scal, i_s, rin, skip, scal2, i_s2);
+    conv_launch_blk(h, net, layer, in, wl, epi, out_act, out_f, mask, scal, i_s, s, rin, skip, scal2, i_s2);
     return;
   }
   int waves = div_up(nout, 64);
@@ -711,34 +770,10 @@ static void conv_launch(qxd_handle* h, int layer, const uint16_t* in, const uint
   }
 }
 
-// Block shape of the tiled convolution: 512 sites, every extent even and
-// dividing the lattice extent, smallest halo that fits the LDS array (ties:
-// the longest x3 extent, which keeps the stores contiguous).  False when the
-// lattice admits none (the per-site gather kernel is used then).
-static bool nn_pick_blocks(const Geo& g, int* bk) {
-  const int ext[4] = {g.Le0, g.Le1, g.Le2, g.Le3};
-  const int cand[5] = {2, 4, 8, 16, 32};
-  int best = -1;
-  for (int a = 0; a < 5; ++a)
-    for (int b = 0; b < 5; ++b)
-      for (int c = 0; c < 5; ++c)
-        for (int d = 0; d < 5; ++d) {
-          int B[4] = {cand[a], cand[b], cand[c], cand[d]};
-          if (B[0] * B[1] * B[2] * B[3] != NN_BLK_SITES) continue;
-          bool ok = true;
-          for (int m = 0; m < 4; ++m) ok = ok && ext[m] % B[m] == 0;
-          int npos = (B[0] + 2) * (B[1] + 2) * (B[2] + 2) * (B[3] + 2);
-          if (!ok || npos > NN_HALO_MAX) continue;
-          if (best < 0 || npos < best || (npos == best && B[3] > bk[3])) {
-            best = npos;
-            for (int m = 0; m < 4; ++m) bk[m] = B[m];
-          }
-        }
-  if (best < 0) return false;
-  bk[4] = g.Le1 / bk[1];
-  bk[5] = g.Le2 / bk[2];
-  bk[6] = g.Le3 / bk[3];
-  return true;
+// The tiled convolution runs when the 4 x 4 x 4 x 8 blocks divide the extended
+// lattice; otherwise the per-site gather kernel does.
+static bool nn_blocks_fit(const Geo& g) {
+  return g.Le0 % NnBlock::B0 == 0 && g.Le1 % NnBlock::B1 == 0 && g.Le2 % NnBlock::B2 == 0 && g.Le3 % NnBlock::B3 == 0;
 }
 
 static qxd_status nn_alloc_act(qxd_nn* net) {
@@ -859,7 +894,11 @@ extern "C" qxd_status qxd_nn_create(qxd_handle* h, qxd_nn** out) {
   if (!net) return QXD_ENOMEM;
   net->h = h;
   const char* gather = getenv("QXD_NN_GATHER");
-  net->blk = !(gather && gather[0] == '1') && nn_pick_blocks(h->geo, net->bk);
+  net->blk = !(gather && gather[0] == '1') && nn_blocks_fit(h->geo);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&net->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || net->ncu < 1)
+    net->ncu = 1;
   size_t n = QXD_NN_NWEIGHTS;
   if (hipMalloc(&net->w, n * 4) != hipSuccess || hipMalloc(&net->m, n * 4) != hipSuccess ||
       hipMalloc(&net->v, n * 4) != hipSuccess || hipMalloc(&net->grad, n * 4) != hipSuccess ||

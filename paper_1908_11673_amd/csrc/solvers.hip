@@ -65,6 +65,46 @@ qxd_status apply_op(qxd_handle* h, InnerOp op, VT* out, const VT* in, double* no
 }
 
 template <class VT>
+qxd_status apply_op_dag(qxd_handle* h, InnerOp op, int dagger, VT* out, const VT* in, double* norm_slot,
+                        hipStream_t s) {
+  if (op.mode == 0) return qxd_schur_apply(h, QXD_F64, dagger, out, in, norm_slot, s);
+  if (op.mode == 1) return qxd_schur_apply(h, QXD_F32, dagger, out, in, norm_slot, s);
+  return qxd_schur_apply_mixed(h, dagger, (float4*)out, (const float4*)in, norm_slot, s);
+}
+
+// CG on the normal equations D_hat^+ D_hat x = D_hat^+ b of the inner operator,
+// x from zero; r holds b on entry and the recursive residual b - D_hat x on
+// exit.  Stops when |r| <= tol_abs (checked every `check` iterations) or after
+// max_steps iterations.  Device scalars: S_ZZ0/1 |z|^2, S_WW |w|^2, S_FRR |r|^2.
+template <class VT>
+qxd_status cgnr(qxd_handle* h, InnerOp op, VT* x, VT* r, VT* p, VT* z, VT* w, size_t n, double tol_abs,
+                int max_steps, int check, int* steps, int64_t* applies, hipStream_t s) {
+  const size_t bytes = n * sizeof(VT);
+  blas_zero<VT>(x, n, s);
+  QXD_TRY(apply_op_dag<VT>(h, op, 1, z, r, h->scal + S_ZZ0, s));
+  QXD_HIP(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, s));
+  *applies += 1;
+  int it = 0;
+  while (it < max_steps) {
+    const int zo = S_ZZ0 + (it & 1), zn = S_ZZ0 + ((it + 1) & 1);
+    QXD_TRY(apply_op_dag<VT>(h, op, 0, w, p, h->scal + S_WW, s));
+    blas_cg_xr<VT>(h, x, r, p, w, n, zo, S_WW, S_FRR, s);
+    QXD_TRY(apply_op_dag<VT>(h, op, 1, z, r, h->scal + zn, s));
+    blas_cg_p<VT>(h, p, z, n, zn, zo, s);
+    *applies += 2;
+    ++it;
+    if (it % check == 0) {
+      QXD_TRY(read_scal(h, S_FRR, 1, s));
+      double rr = h->scal_host[S_FRR];
+      if (!std::isfinite(rr)) return QXD_ENAN;
+      if (std::sqrt(rr) <= tol_abs) break;
+    }
+  }
+  *steps = it;
+  return QXD_OK;
+}
+
+template <class VT>
 qxd_status precond_apply(qxd_handle* h, qxd_nn* net, VT* out, const VT* in, hipStream_t s);
 template <>
 qxd_status precond_apply<float4>(qxd_handle* h, qxd_nn* net, float4* out, const float4* in, hipStream_t s) {
@@ -194,6 +234,69 @@ qxd_status check_params(const qxd_solver_params* p) {
   return QXD_OK;
 }
 
+// Defect correction around an FP32 (or bfloat16-link) CG: r = bhat - D_hat x in
+// FP64; the inner CG solves D_hat e = r / |r| on the normal equations to the
+// relative residual max(inner_res, tol / (2 |r|)); x += |r| e in FP64.
+qxd_status solve_cg_dc(qxd_handle* h, const qxd_solver_params* prm, void* x, const void* b,
+                       qxd_solver_stats* stats, void* stream, clk::time_point t0) {
+  hipStream_t s = as_stream(stream);
+  size_t n64 = (size_t)12 * h->Ve, n32 = (size_t)6 * h->Ve;
+  size_t b64 = n64 * sizeof(double2), b32 = n32 * sizeof(float4);
+  double2 *bh = (double2*)ws_get(h, W_BH, b64), *xe = (double2*)ws_get(h, W_XE, b64);
+  double2 *r = (double2*)ws_get(h, W_R, b64), *w = (double2*)ws_get(h, W_W, b64);
+  float4 *r32 = (float4*)ws_get(h, W_R32, b32), *e32 = (float4*)ws_get(h, W_E32, b32);
+  float4 *p32 = (float4*)ws_get(h, W_P, b32), *z32 = (float4*)ws_get(h, W_Z, b32);
+  float4* w32 = (float4*)ws_get(h, W_E64, b32);
+  if (!bh || !xe || !r || !w || !r32 || !e32 || !p32 || !z32 || !w32) return QXD_ENOMEM;
+  qxd_solver_stats st{};
+  double nb;
+  qxd_status rc = norm_full(h, (const double2*)b, &nb, s);
+  if (rc != QXD_OK) return rc;
+  const double tol = prm->res * nb;
+  QXD_TRY(qxd_eo_source(h, bh, b, s));
+  blas_zero<double2>(xe, n64, s);
+  QXD_HIP(hipMemcpyAsync(r, bh, b64, hipMemcpyDeviceToDevice, s));
+  blas_norm2<double2>(h, r, n64, h->scal + S_RR, s);
+  QXD_TRY(read_scal(h, S_RR, 1, s));
+  double rr = h->scal_host[S_RR];
+  const int max_outer = prm->max_outer > 0 ? prm->max_outer : 100;
+  const double inner_res = prm->inner_res > 0 ? prm->inner_res : 1e-5;
+  const int check = prm->check_every > 0 ? prm->check_every : 1;
+  int steps_left = prm->nmx;
+  InnerOp op{prm->inner_prec == QXD_F32 ? 1 : 2};
+  rc = QXD_ENOCONV;
+  for (int outer = 0; outer < max_outer; ++outer) {
+    if (!std::isfinite(rr)) { rc = QXD_ENAN; break; }
+    double rn = std::sqrt(rr);
+    if (rn <= tol) { rc = QXD_OK; break; }
+    if (steps_left <= 0) break;
+    blas_down(h, r32, r, S_RR, s);
+    int steps = 0;
+    qxd_status ic = cgnr<float4>(h, op, e32, r32, p32, z32, w32, n32, std::fmax(inner_res, 0.5 * tol / rn),
+                                 steps_left, check, &steps, &st.schur_applies, s);
+    if (ic != QXD_OK) { rc = ic; break; }
+    blas_up_acc(h, xe, e32, S_RR, s);
+    st.inner_it += steps;
+    steps_left -= steps;
+    st.outer_it = outer + 1;
+    QXD_TRY(qxd_schur_apply(h, QXD_F64, 0, w, xe, nullptr, s));
+    st.schur_applies++;
+    blas_sub_norm<double2>(h, r, bh, w, n64, h->scal + S_RR, s);
+    QXD_TRY(read_scal(h, S_RR, 1, s));
+    rr = h->scal_host[S_RR];
+    if (steps == 0 && !(std::sqrt(rr) <= tol)) break;
+  }
+  if (rc == QXD_OK || rc == QXD_ENOCONV) {
+    QXD_TRY(qxd_eo_reconstruct(h, x, xe, b, s));
+    QXD_TRY(true_residual(h, (const double2*)x, (const double2*)b, nb, &st.true_residual, s));
+    if (rc == QXD_OK && !(st.true_residual <= prm->res)) rc = QXD_ENOCONV;
+  }
+  st.status = rc;
+  st.t_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  if (stats) *stats = st;
+  return rc;
+}
+
 }  // namespace
 
 extern "C" qxd_status qxd_solve_cg(qxd_handle* h, const qxd_solver_params* prm, void* x, const void* b,
@@ -202,6 +305,8 @@ extern "C" qxd_status qxd_solve_cg(qxd_handle* h, const qxd_solver_params* prm, 
   if (!h || !x || !b) return QXD_EINVAL;
   QXD_TRY(check_params(prm));
   if (!h->has_inverse) return QXD_ESTATE;
+  if (prm->inner_prec == QXD_F32 || prm->inner_prec == QXD_BF16) return solve_cg_dc(h, prm, x, b, stats, stream, t0);
+  if (prm->inner_prec != QXD_F64) return QXD_EINVAL;
   hipStream_t s = as_stream(stream);
   size_t n = (size_t)12 * h->Ve;
   size_t bytes = n * sizeof(double2);

@@ -41,10 +41,22 @@ def test_cg_f64_c0(c0):
     o, lat, b, x_ref = c0
     bd = lat.pack(to_dev(b))
     x = lat.field(qxd.F64, full=True)
-    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10), x, bd)
+    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F64), x, bd)
     print(st)
-    assert st["status"] == 0 and st["true_residual"] <= 1e-10
+    assert st["status"] == 0 and st["true_residual"] <= 1e-10 and st["outer_it"] == 1
     _check_solution(o, b, lat.unpack(x).cpu().numpy(), x_ref, "cg")
+
+
+@pytest.mark.parametrize("inner", [qxd.F32, qxd.BF16], ids=["f32", "bf16links"])
+def test_defect_correction_cg_c0(c0, inner):
+    """FP64 defect correction around an FP32 (bf16-link) CG on the normal equations."""
+    o, lat, b, x_ref = c0
+    bd = lat.pack(to_dev(b))
+    x = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner), x, bd)
+    print(st)
+    assert st["status"] == 0 and st["true_residual"] <= 1e-10 and st["outer_it"] >= 2
+    _check_solution(o, b, lat.unpack(x).cpu().numpy(), x_ref, "dc-cg%d" % inner)
 
 
 @pytest.mark.parametrize("inner", [qxd.F64, qxd.F32, qxd.BF16], ids=["f64", "f32", "bf16links"])
@@ -72,8 +84,10 @@ def test_solves_are_deterministic(c0):
 def test_enoconv_when_iteration_limit_hit(c0):
     o, lat, b, _ = c0
     x = lat.field(qxd.F64, full=True)
-    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(nmx=1, res=1e-10), x, lat.pack(to_dev(b)), check=False)
-    assert st["status"] == 6
+    for inner in (qxd.F64, qxd.F32):
+        st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(nmx=1, res=1e-10, inner_prec=inner), x, lat.pack(to_dev(b)),
+                              check=False)
+        assert st["status"] == 6
     st = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(nmx=1, res=1e-10), None, x, lat.pack(to_dev(b)), check=False)
     assert st["status"] == 6
 
@@ -83,8 +97,9 @@ def test_enan_on_nan_source(c0):
     bb = b.copy()
     bb[3, 1, 2] = np.nan
     x = lat.field(qxd.F64, full=True)
-    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(), x, lat.pack(to_dev(bb)), check=False)
-    assert st["status"] == 5
+    for inner in (qxd.F64, qxd.F32):
+        st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(inner_prec=inner), x, lat.pack(to_dev(bb)), check=False)
+        assert st["status"] == 5
     st = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(), None, x, lat.pack(to_dev(bb)), check=False)
     assert st["status"] == 5
 
