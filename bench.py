@@ -257,9 +257,10 @@ def copy_calibration(torch):
 
 def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs):
     """Time to a true FP64 residual 1e-10 on the benchmark lattice, one Gaussian
-    source per flavour: FP64 CG against FP32-inner FGCR, bf16-link-inner FGCR,
-    and FP32-inner FGCR preconditioned by a network trained (per flavour) on pairs
-    harvested from seeded 32 x 16^3 fields with the same statistics."""
+    source per flavour: FP64 CG against defect-correction CG and FGCR with FP32
+    and bf16-link inner solves, and FP32-inner FGCR preconditioned by a network
+    trained (per flavour) on pairs harvested from seeded 32 x 16^3 fields with
+    the same statistics."""
     import synthgen as sg
     from paper_1908_11673_amd import learned
     c3 = sg.WORKLOADS["c3"]
@@ -286,16 +287,19 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs):
                 info["loss_history"][-1]))
         bd = lat.pack(torch.from_numpy(b).cuda())
         x = lat.field(qxd.F64, full=True)
-        legs = [("cg_f64", lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F64, check_every=8), x, bd,
-                                                     check=False)),
-                ("fgcr_f32_in_f64", lambda: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10,
-                                                                                        inner_prec=qxd.F32),
-                                                               None, x, bd, check=False)),
-                ("fgcr_bf16links_in_f64", lambda: qxd.qxd_solve_fgcr(
-                    lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.BF16), None, x, bd, check=False))]
+
+        def cg(inner):
+            return lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner, check_every=8), x,
+                                            bd, check=False)
+
+        def fgcr(inner, network=None):
+            return lambda: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner), network, x, bd,
+                                              check=False)
+
+        legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16)),
+                ("fgcr_f32_in_f64", fgcr(qxd.F32)), ("fgcr_bf16links_in_f64", fgcr(qxd.BF16))]
         if net is not None:
-            legs.append(("fgcr_f32_nn_in_f64", lambda: qxd.qxd_solve_fgcr(
-                lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32), net, x, bd, check=False)))
+            legs.append(("fgcr_f32_nn_in_f64", fgcr(qxd.F32, net)))
         for tag, fn in legs:
             times = []
             for rep in range(3):

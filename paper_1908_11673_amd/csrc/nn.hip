@@ -260,56 +260,60 @@ struct NnTapList {
   }
 };
 
-// The tap loop, fully unrolled: the weights of tap k + NN_WPF are requested
-// while tap k is contracted, and the LDS operands of tap k + 1 are read before
-// the matrix-core instructions of tap k.  raddr[rb][d3 + 1] is the byte
+// The tap loop, fully unrolled: the weights of tap k + NN_WPF and the LDS
+// operands of tap k + NN_APF are requested while tap k is contracted, on NCB
+// column tiles of 16 output channels starting at tile cb0.  raddr[rb][d3 + 1] is the byte
 // address of row rb's neighbour at (-1, -1, -1, d3); tap (d0, d1, d2, d3)
 // adds the constant (d0 + 1) T0 + (d1 + 1) T1 + (d2 + 1) T2.
+#ifndef NN_WPF
 #define NN_WPF 8
+#endif
 #ifndef NN_WAVES
 #define NN_WAVES 8  // waves per workgroup of the block kernel
 #endif
-template <class SH, bool SPARSE, int P, int RB>
+#ifndef NN_APF
+#define NN_APF 2  // taps ahead whose LDS operands are in flight
+#endif
+template <class SH, bool SPARSE, int P, int RB, int NCB>
 __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __restrict__ W, const int (&raddr)[RB][3],
-                                            int lr, int kc, f4v (&acc)[RB][2]) {
+                                            int lr, int kc, int cb0, f4v (&acc)[RB][NCB]) {
   constexpr NnTapList<SPARSE, P> TL{};
-  static_assert(TL.n > NN_WPF, "weight prefetch deeper than the tap list");
-  bf16x8 wb[NN_WPF][2];
-#pragma unroll
-  for (int k = 0; k < NN_WPF; ++k) {
-    const uint16_t* wt = W + TL.t[k] * (NN_C * NN_C);
-    wb[k][0] = ld8(wt + lr * NN_C + kc);
-    wb[k][1] = ld8(wt + (16 + lr) * NN_C + kc);
-  }
+  static_assert(TL.n > NN_WPF && TL.n > NN_APF, "prefetch deeper than the tap list");
+  auto wld = [&](int tap, int cb) {
+    return ld8(W + tap * (NN_C * NN_C) + ((cb0 + cb) * 16 + lr) * NN_C + kc);
+  };
   auto rd = [&](int rb, int tap) {
     const int off = (tap / 27) * SH::T0 + (tap / 9 % 3) * SH::T1 + (tap / 3 % 3) * SH::T2;
     return *reinterpret_cast<const bf16x8*>(lds + raddr[rb][tap % 3] + off);
   };
-  bf16x8 a[RB];
+  bf16x8 wb[NN_WPF][NCB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) a[rb] = rd(rb, TL.t[0]);
+  for (int k = 0; k < NN_WPF; ++k)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) wb[k][cb] = wld(TL.t[k], cb);
+  bf16x8 a[NN_APF + 1][RB];
+#pragma unroll
+  for (int k = 0; k < NN_APF; ++k)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) a[k][rb] = rd(rb, TL.t[k]);
 #pragma unroll
   for (int k = 0; k < TL.n; ++k) {
-    bf16x8 w0 = wb[k % NN_WPF][0], w1 = wb[k % NN_WPF][1];
+    bf16x8 w[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) w[cb] = wb[k % NN_WPF][cb];
     if (k + NN_WPF < TL.n) {
-      const uint16_t* wt = W + TL.t[k + NN_WPF] * (NN_C * NN_C);
-      wb[k % NN_WPF][0] = ld8(wt + lr * NN_C + kc);
-      wb[k % NN_WPF][1] = ld8(wt + (16 + lr) * NN_C + kc);
-    }
-    bf16x8 an[RB];
-    if (k + 1 < TL.n) {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) an[rb] = rd(rb, TL.t[k + 1]);
+      for (int cb = 0; cb < NCB; ++cb) wb[k % NN_WPF][cb] = wld(TL.t[k + NN_WPF], cb);
+    }
+    if (k + NN_APF < TL.n) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) a[(k + NN_APF) % (NN_APF + 1)][rb] = rd(rb, TL.t[k + NN_APF]);
     }
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], w0, acc[rb][0], 0, 0, 0);
-      acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], w1, acc[rb][1], 0, 0, 0);
-    }
-    if (k + 1 < TL.n) {
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) a[rb] = an[rb];
-    }
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k % (NN_APF + 1)][rb], w[cb], acc[rb][cb], 0, 0, 0);
   }
 }
 
@@ -401,12 +405,16 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
     o3 = c3 * SH::B3;
   };
 
-  // NW waves share the 32 row tiles (16 of each parity; 16 even ones only with EVEN_OUT)
-  constexpr int RB = (EVEN_OUT ? 16 : 32) / NW;
+  // NW waves share the 32 row tiles (16 of each parity) and both column tiles;
+  // with EVEN_OUT the 16 even row tiles, each wave one column tile (so that a
+  // weight tile loaded still feeds as many matrix-core instructions)
+  constexpr int NCB = EVEN_OUT ? 1 : 2;
+  constexpr int RB = 32 / NW;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int lr = l & 15, kc = (l >> 4) * 8, ch = l >> 4;
   const int p = EVEN_OUT ? 0 : wave / (NW / 2);
-  const int g0 = EVEN_OUT ? wave : wave % (NW / 2), gstep = EVEN_OUT ? NW : NW / 2;
+  const int cb0 = EVEN_OUT ? (wave & 1) : 0;
+  const int g0 = EVEN_OUT ? (wave >> 1) : wave % (NW / 2), gstep = NW / 2;
   int raddr[RB][3];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
@@ -426,19 +434,19 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
     origin(b, o0, o1, o2, o3);
     nn_halo_stage<SH, NW, SPARSE_IN>(g, in, lds, o0, o1, o2, o3);
     __syncthreads();
-    f4v acc[RB][2];
+    f4v acc[RB][NCB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
+      for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
     // the weight loads do not depend on the block: keep the compiler from
     // hoisting all 81 taps' worth out of the block loop
     const uint16_t* Wb = W;
     asm volatile("" : "+s"(Wb));
     if (!SPARSE_IN || p == 0)
-      nn_blk_taps<SH, SPARSE_IN, 0, RB>(lds, Wb, raddr, lr, kc, acc);
+      nn_blk_taps<SH, SPARSE_IN, 0, RB, NCB>(lds, Wb, raddr, lr, kc, cb0, acc);
     else
-      nn_blk_taps<SH, SPARSE_IN, 1, RB>(lds, Wb, raddr, lr, kc, acc);
+      nn_blk_taps<SH, SPARSE_IN, 1, RB, NCB>(lds, Wb, raddr, lr, kc, cb0, acc);
     __syncthreads();  // every wave is done with the halo: the LDS takes the output tile
     const int hb = geo_half(g, o0, o1, o2, o3);
     if (EPI == EPI_SPINOR) {
@@ -447,11 +455,11 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             int j = (g0 + rb * gstep) * 16 + (l >> 4) * 4 + i;
-            int c = cb * 16 + lr;
+            int c = (cb0 + cb) * 16 + lr;
             if (c < 24) st[j * 24 + c] = acc[rb][cb][i];
           }
       __syncthreads();
@@ -482,12 +490,12 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             int s = p * (NN_BLK_SITES / 2) + (g0 + rb * gstep) * 16 + (l >> 4) * 4 + i;
             float vv = acc[rb][cb][i];
-            st[s * NN_C + cb * 16 + lr] = f2bf(EPI == EPI_RELU ? fmaxf(vv, 0.f) : vv);
+            st[s * NN_C + (cb0 + cb) * 16 + lr] = f2bf(EPI == EPI_RELU ? fmaxf(vv, 0.f) : vv);
           }
       __syncthreads();
 #pragma unroll
