@@ -98,7 +98,10 @@ def main():
     import synthgen as sg
 
     w = sg.WORKLOADS[args.workload]
-    flavours = [sg.FLAVOURS["d"], sg.FLAVOURS["u"]]
+    # the 128 x 64^3 lattice (175 GB of links and clover per flavour) runs one
+    # flavour, one buffer pair, and releases the gauge copy after set-up
+    big = args.workload == "c4"
+    flavours = [sg.FLAVOURS["d"]] if big else [sg.FLAVOURS["d"], sg.FLAVOURS["u"]]
     log("generating %s fields %s" % (args.workload, w["L"]))
     U, A = make_fields(w)
     lats = []
@@ -106,11 +109,13 @@ def main():
         lat = qxd.Lattice(w["L"], w["cstar"])
         st = lat.setup(U, A, f)
         log("flavour qhat=%d: clover min pivot %.4f" % (f["qhat"], st["min_pivot"]))
+        if big:
+            qxd.qxd_trim(lat.h)
         lats.append(lat)
     Ve = lats[0].Ve
     torch.cuda.synchronize()
 
-    nbuf = 4
+    nbuf = 1 if big else 4
     psi = sg.spinor(w["source_seed"], lats[0].V)
     src64 = lats[0].pack(torch.from_numpy(psi).cuda())
     src32 = lats[0].pack(torch.from_numpy(psi).cuda(), qxd.F32)
@@ -122,7 +127,7 @@ def main():
             t.copy_(src[:12 * Ve] * (1.0 + 0.01 * i))
             ins[p].append(t)
             outs[p].append(qxd.field(Ve, p))
-    del psi
+    del psi, src64, src32
 
     stream = torch.cuda.current_stream()
     sptr = stream.cuda_stream
@@ -185,8 +190,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "D_hat applies, 32^3x64 physical with C* in 3 directions "
-                               "(extended 64x64x32x32), 2 flavours x {FP64, FP32} per step",
+        "config": {"workload": "D_hat applies, %dx%d^3 physical with C* in %d directions (extended %dx%dx%dx%d), "
+                               "%d flavour%s x {FP64, FP32} per step" % (
+                                   w["L"][0], w["L"][1], w["cstar"], w["L"][0], 2 * w["L"][1], w["L"][2], w["L"][3],
+                                   len(flavours), "s" if len(flavours) > 1 else ""),
                    "extended_lattice": [w["L"][0], 2 * w["L"][1], w["L"][2], w["L"][3]],
                    "even_sites": Ve, "flavours": [{"qhat": f["qhat"], "kappa": f["kappa"]} for f in flavours],
                    "parallelism": "single GPU"},
@@ -199,9 +206,12 @@ def main():
     }
 
     if not args.no_solve:
-        result["time_to_solution"] = solve_leg(qxd, torch, lats, w, flavours, args.nn_fields, args.nn_epochs)
+        del ins, outs
+        torch.cuda.empty_cache()
+        result["time_to_solution"] = solve_leg(qxd, torch, lats, w, flavours, 0 if big else args.nn_fields,
+                                               args.nn_epochs, big)
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not big:  # the oracle would hold 60 GB of host fields at 128 x 64^3
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(w, U, A, flavours[0], args.cpu_seconds)
     print(json.dumps(result), flush=True)
@@ -255,7 +265,7 @@ def copy_calibration(torch):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
-def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs):
+def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False):
     """Time to a true FP64 residual 1e-10 on the benchmark lattice, one Gaussian
     source per flavour: FP64 CG against defect-correction CG and FGCR with FP32
     and bf16-link inner solves, and FP32-inner FGCR preconditioned by a network
@@ -286,6 +296,7 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs):
                 name, info["pairs"], info["harvest_s"], info["train_s"], info["loss_history"][0],
                 info["loss_history"][-1]))
         bd = lat.pack(torch.from_numpy(b).cuda())
+        torch.cuda.empty_cache()  # the library allocates its solver vectors itself
         x = lat.field(qxd.F64, full=True)
 
         def cg(inner):
@@ -296,13 +307,14 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs):
             return lambda: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner), network, x, bd,
                                               check=False)
 
-        legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16)),
-                ("fgcr_f32_in_f64", fgcr(qxd.F32)), ("fgcr_bf16links_in_f64", fgcr(qxd.BF16))]
+        legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16))]
+        if not big:  # FGCR's 2 nkv direction vectors do not fit beside the 128 x 64^3 operator
+            legs += [("fgcr_f32_in_f64", fgcr(qxd.F32)), ("fgcr_bf16links_in_f64", fgcr(qxd.BF16))]
         if net is not None:
             legs.append(("fgcr_f32_nn_in_f64", fgcr(qxd.F32, net)))
         for tag, fn in legs:
             times = []
-            for rep in range(3):
+            for rep in range(1 if big else 3):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 st = fn()

@@ -130,6 +130,15 @@ qxd_status qxd_destroy(qxd_handle *h);
 /* Extended volume V and Ve = V/2. */
 qxd_status qxd_volume(const qxd_handle *h, int64_t *V, int64_t *Ve);
 
+/* Release the memory a set-up handle no longer needs for applying D, D_hat or
+ * solving: the device copy of the physical gauge field and every solver and
+ * Schur workspace (these are allocated again when next used).  Links, clover
+ * blocks and their inverse stay.  Afterwards qxd_set_flavour and
+ * qxd_clover_build return QXD_ESTATE until qxd_set_gauge is called again.  On
+ * the largest lattices this is what leaves room for the solver vectors (about
+ * 20 GB at 128 x 64^3 physical).  Synchronises the device. */
+qxd_status qxd_trim(qxd_handle *h);
+
 /* Gauge fields on the physical lattice: U_phys [4][Vphys][3][3] complex128 (row,
  * column), A_phys [4][Vphys] float64, Vphys = L0 L1 L2 L3, physical site index
  * x3 + L3 (x2 + L2 (x1 + L1 x0)).  on_device != 0: device pointers, else host
@@ -139,11 +148,13 @@ qxd_status qxd_set_gauge(qxd_handle *h, const double *U_phys, const double *A_ph
 
 /* Select the flavour and build the combined links V(x,mu) = U(x,mu) z(x,mu)^qhat
  * (Sec. 2.3, covariant derivatives) on the extended lattice in every storage
- * precision.  Invalidates the clover until the next clover_build/invert. */
+ * precision.  Invalidates the clover until the next clover_build/invert.
+ * QXD_ESTATE without a gauge field (none set yet, or released by qxd_trim). */
 qxd_status qxd_set_flavour(qxd_handle *h, const qxd_flavour *f, void *stream);
 
 /* SW term (Sec. 2.3): the site-diagonal 1/(2 kappa) + dD_sw on every site, as two
- * Hermitian 6x6 chirality blocks. */
+ * Hermitian 6x6 chirality blocks.  QXD_ESTATE without a flavour or after
+ * qxd_trim released the gauge field. */
 qxd_status qxd_clover_build(qxd_handle *h, void *stream);
 
 /* Invert the odd-site blocks (D_oo^-1 in Sec. 2.3's Schur complement) in FP64

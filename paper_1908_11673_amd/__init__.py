@@ -80,6 +80,7 @@ _SIGNATURES = {
     "qxd_create": ([ctypes.POINTER(qxd_geom), ctypes.POINTER(_P)], _I),
     "qxd_destroy": ([_P], _I),
     "qxd_volume": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
+    "qxd_trim": ([_P], _I),
     "qxd_set_gauge": ([_P, _P, _P, _I, _P], _I),
     "qxd_set_flavour": ([_P, ctypes.POINTER(qxd_flavour), _P], _I),
     "qxd_clover_build": ([_P, _P], _I),
@@ -165,6 +166,10 @@ def qxd_create(L, cstar, t_antiperiodic=False):
 
 def qxd_destroy(h):
     _check(load().qxd_destroy(h), "qxd_destroy")
+
+
+def qxd_trim(h):
+    _check(load().qxd_trim(h), "qxd_trim")
 
 
 def qxd_volume(h):

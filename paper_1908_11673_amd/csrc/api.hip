@@ -89,6 +89,25 @@ extern "C" qxd_status qxd_destroy(qxd_handle* h) {
   return QXD_OK;
 }
 
+extern "C" qxd_status qxd_trim(qxd_handle* h) {
+  if (!h) return QXD_EINVAL;
+  QXD_HIP(hipDeviceSynchronize());
+  void** ptrs[] = {reinterpret_cast<void**>(&h->Uphys), reinterpret_cast<void**>(&h->Aphys),
+                   reinterpret_cast<void**>(&h->t64), reinterpret_cast<void**>(&h->t32),
+                   reinterpret_cast<void**>(&h->t16)};
+  for (void** p : ptrs) {
+    if (*p) QXD_HIP(hipFree(*p));
+    *p = nullptr;
+  }
+  for (int i = 0; i < 64; ++i) {
+    if (h->ws[i]) QXD_HIP(hipFree(h->ws[i]));
+    h->ws[i] = nullptr;
+    h->ws_bytes[i] = 0;
+  }
+  h->has_gauge = false;
+  return QXD_OK;
+}
+
 extern "C" qxd_status qxd_volume(const qxd_handle* h, int64_t* V, int64_t* Ve) {
   if (!h) return QXD_EINVAL;
   if (V) *V = h->V;

@@ -355,7 +355,7 @@ static qxd_status alloc_clover(qxd_handle* h) {
 
 extern "C" qxd_status qxd_clover_build(qxd_handle* h, void* stream) {
   if (!h) return QXD_EINVAL;
-  if (!h->has_flavour) return QXD_ESTATE;
+  if (!h->has_flavour || !h->Uphys) return QXD_ESTATE;
   QXD_TRY(alloc_clover(h));
   hipStream_t s = as_stream(stream);
   PhysExt2 pe;

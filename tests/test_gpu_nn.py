@@ -155,7 +155,7 @@ def test_block_and_gather_kernels_agree():
         qxd.qxd_nn_set_skip(net, 0.1)
         out = lat.field(qxd.F32)
         qxd.qxd_nn_apply(lat.h, net, out, half32(lat, o, r))
-        outs.append(out.cpu().double())
+        outs.append(out.cpu().to(torch.complex128))
         qxd.qxd_nn_destroy(net)
     err = float(torch.linalg.norm(outs[0] - outs[1]) / torch.linalg.norm(outs[1]))
     print("block vs gather rel diff %.2e" % err)

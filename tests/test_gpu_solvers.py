@@ -119,3 +119,33 @@ def test_esingular_on_exactly_singular_clover():
     st = qxd.qxd_clover_invert(lat.h, check=False)
     assert st["status"] == 4 and st["n_singular"] >= 1
     lat.close()
+
+
+def test_trim_keeps_the_operator_and_blocks_rebuilding():
+    """qxd_trim frees the gauge copy and the workspaces: D_hat and solves are
+    unchanged afterwards, flavour/clover rebuilds need the gauge field again."""
+    o, lat, _ = make_pair((4, 4, 4, 8), 3, FD, sigma=0.2, su1=0.3, seed=5)
+    b = sg.spinor(77, o.V)
+    bd = lat.pack(to_dev(b))
+    psi = lat.pack(to_dev(sg.spinor(78, o.V)))[:12 * lat.Ve].clone()
+    before = lat.field(qxd.F64)
+    qxd.qxd_dw_eo_schur(lat.h, qxd.F64, 0, before, psi)
+    x0 = lat.field(qxd.F64, full=True)
+    qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F64), x0, bd)
+    qxd.qxd_trim(lat.h)
+    after = lat.field(qxd.F64)
+    qxd.qxd_dw_eo_schur(lat.h, qxd.F64, 0, after, psi)
+    assert torch.equal(before, after)
+    x1 = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F64), x1, bd)
+    assert st["status"] == 0 and torch.equal(x0, x1)
+    f = qxd.qxd_flavour(FD["qhat"], FD["invqel"], FD["kappa"], FD["su3csw"], FD["u1csw"])
+    assert qxd.load().qxd_set_flavour(lat.h, qxd.ctypes.byref(f), None) == 8
+    assert qxd.load().qxd_clover_build(lat.h, None) == 8
+    U = sg.gauge_su3(5, 0.2, o.Vphys)
+    A = sg.gauge_u1(5, 0.3, o.Vphys)
+    lat.setup(U, A, FD)
+    again = lat.field(qxd.F64)
+    qxd.qxd_dw_eo_schur(lat.h, qxd.F64, 0, again, psi)
+    assert torch.equal(before, again)
+    lat.close()
