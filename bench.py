@@ -219,7 +219,8 @@ def main():
         lat.close()
 
 
-TRAFFIC_SOURCES = ("paper_1908_11673_amd/csrc/dirac.hip", "paper_1908_11673_amd/csrc/qxd_internal.hpp",
+TRAFFIC_SOURCES = ("paper_1908_11673_amd/csrc/dirac.hip", "paper_1908_11673_amd/csrc/wilson_site.hpp",
+                   "paper_1908_11673_amd/csrc/qxd_internal.hpp",
                    "paper_1908_11673_amd/build.py")
 
 

@@ -102,6 +102,8 @@ typedef struct {
   int max_outer;       /* defect-correction steps limit */
   int check_every;     /* CG: read the residual back every this many iterations */
   int fallback_after;  /* NN FGCR: inner steps without progress before dropping M */
+  int sap_ncy;         /* FGCR: > 0 selects the SAP preconditioner with this many cycles (net must be NULL) */
+  int sap_nmr;         /* SAP: minimal-residual steps per block solve */
 } qxd_solver_params;
 
 typedef struct {
@@ -112,7 +114,8 @@ typedef struct {
   int64_t nn_applies;  /* preconditioner network applications */
   double true_residual;/* FP64 |b - D x| / |b| on the full lattice, recomputed */
   double t_ms;         /* wall time of the call */
-  int fell_back;       /* 1 if the network preconditioner was dropped */
+  int fell_back;       /* 1 if the preconditioner was dropped */
+  int64_t sap_applies; /* SAP preconditioner applications */
 } qxd_solver_stats;
 
 typedef struct qxd_handle qxd_handle;
@@ -203,6 +206,20 @@ qxd_status qxd_solve_cg(qxd_handle *h, const qxd_solver_params *params, void *x,
  * non-finite or the residual stalls for fallback_after steps. */
 qxd_status qxd_solve_fgcr(qxd_handle *h, const qxd_solver_params *params, qxd_nn *net, void *x, const void *b,
                           qxd_solver_stats *stats, void *stream);
+
+/* SAP, the paper's Schwarz alternating procedure preconditioner (Sec. 4.4,
+ * SAP+GCR), applied to the Schur system: out_e = (M (in_e, 0))_e, where M is
+ * ncy cycles of SAP on the full operator D in FP32 from x = 0.  The extended
+ * lattice is cut into 4^4 blocks coloured by the parity of their block
+ * coordinates; a cycle visits colour 0 then colour 1 and, on every block of
+ * that colour, takes the residual r = eta - D x, runs nmr minimal-residual
+ * steps on D restricted to the block (hops leaving it dropped) and adds the
+ * block solution to x.  (Exact block elimination would make out_e = D_hat^-1
+ * in_e.)  in_e, out_e: FP32 even half fields (device, distinct).  QXD_EGEOM
+ * unless every extended extent is a multiple of 8 and, with C* in k >= 2, L1 is
+ * a multiple of 8; QXD_EINVAL for ncy or nmr outside 1..64; QXD_ESTATE before
+ * the clover inverse.  Also the FGCR preconditioner (qxd_solver_params.sap_ncy). */
+qxd_status qxd_sap_apply(qxd_handle *h, int ncy, int nmr, void *out_e, const void *in_e, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Learned preconditioner: three 3^4-tap convolutions on the extended lattice

@@ -376,5 +376,8 @@ void launch_final_sum(const double* partial, int n, int nvals, int stride, doubl
 qxd_status qxd_schur_apply(qxd_handle* h, qxd_prec p, int dagger, void* out_e, const void* in_e, double* norm_slot,
                            hipStream_t s);
 qxd_status nn_apply_internal(qxd_handle* h, qxd_nn* net, float4* out_e, const float4* in_e, hipStream_t s);
+// SAP preconditioner of the Schur system (sap.hip): out_e = (M_SAP (in_e, 0))_e
+bool sap_supported(const qxd_handle* h);
+qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, float4* out_e, const float4* in_e, hipStream_t s);
 qxd_status qxd_schur_apply_mixed(qxd_handle* h, int dagger, float4* out_e, const float4* in_e, double* norm_slot,
                                  hipStream_t s);

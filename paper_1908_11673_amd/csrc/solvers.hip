@@ -19,7 +19,7 @@ using clk = std::chrono::steady_clock;
 // workspace roles
 enum {
   W_BH = 0, W_XE, W_R, W_P, W_Z, W_W, W_FULL0, W_FULL1,  // FP64 halves (FULL*: full fields)
-  W_R32 = 10, W_E32, W_E64,
+  W_R32 = 10, W_E32, W_E64,  // 13: the SAP iterate's odd half (sap.hip)
   W_PHI = 16,    // 16..(16+QXD_MAXKV-1)
   W_CHI = 40     // 40..(40+QXD_MAXKV-1) -> needs ws[] of 64+: keep nkv <= 24
 };
@@ -104,14 +104,22 @@ qxd_status cgnr(qxd_handle* h, InnerOp op, VT* x, VT* r, VT* p, VT* z, VT* w, si
   return QXD_OK;
 }
 
+// The right preconditioner of the inner FGCR: the network or SAP (FP32 only).
+struct Precond {
+  qxd_nn* net = nullptr;
+  int sap_ncy = 0, sap_nmr = 0;
+  bool any() const { return net != nullptr || sap_ncy > 0; }
+};
+
 template <class VT>
-qxd_status precond_apply(qxd_handle* h, qxd_nn* net, VT* out, const VT* in, hipStream_t s);
+qxd_status precond_apply(qxd_handle* h, const Precond& pc, VT* out, const VT* in, hipStream_t s);
 template <>
-qxd_status precond_apply<float4>(qxd_handle* h, qxd_nn* net, float4* out, const float4* in, hipStream_t s) {
-  return nn_apply_internal(h, net, out, in, s);
+qxd_status precond_apply<float4>(qxd_handle* h, const Precond& pc, float4* out, const float4* in, hipStream_t s) {
+  if (pc.net) return nn_apply_internal(h, pc.net, out, in, s);
+  return sap_apply_internal(h, pc.sap_ncy, pc.sap_nmr, out, in, s);
 }
 template <>
-qxd_status precond_apply<double2>(qxd_handle*, qxd_nn*, double2*, const double2*, hipStream_t) {
+qxd_status precond_apply<double2>(qxd_handle*, const Precond&, double2*, const double2*, hipStream_t) {
   return QXD_EINVAL;
 }
 
@@ -119,6 +127,7 @@ struct FgcrResult {
   int steps = 0;
   int64_t applies = 0;
   int64_t nn_applies = 0;
+  int64_t sap_applies = 0;
   bool fell_back = false;
   double rr = 0.0;  // final recursive |r|^2
 };
@@ -128,7 +137,7 @@ struct FgcrResult {
 // previous directions, normalisation, then r -= (chi_k, r) chi_k; at the end of
 // each cycle x += Phi alpha with R alpha = c solved on the host in FP64.
 template <class VT>
-qxd_status fgcr(qxd_handle* h, InnerOp op, qxd_nn* net, int fallback_after, VT* x, VT* r, size_t n, int nkv,
+qxd_status fgcr(qxd_handle* h, InnerOp op, Precond pc, int fallback_after, VT* x, VT* r, size_t n, int nkv,
                 double tol_abs, int max_steps, FgcrResult* res, hipStream_t s,
                 const std::function<qxd_status()>* on_cycle = nullptr) {
   std::vector<VT*> phi(nkv), chi(nkv);
@@ -143,7 +152,7 @@ qxd_status fgcr(qxd_handle* h, InnerOp op, qxd_nn* net, int fallback_after, VT* 
   QXD_TRY(read_scal(h, S_FRR, 1, s));
   double rr = h->scal_host[S_FRR];
   if (!std::isfinite(rr)) return QXD_ENAN;
-  bool use_nn = net != nullptr;
+  bool use_nn = pc.any();
   double best = std::sqrt(rr);
   int since_best = 0;
   int steps = 0;
@@ -154,8 +163,11 @@ qxd_status fgcr(qxd_handle* h, InnerOp op, qxd_nn* net, int fallback_after, VT* 
       while (redo) {
         redo = false;
         if (use_nn) {
-          QXD_TRY(precond_apply<VT>(h, net, phi[k], r, s));
-          res->nn_applies++;
+          QXD_TRY(precond_apply<VT>(h, pc, phi[k], r, s));
+          if (pc.net)
+            res->nn_applies++;
+          else
+            res->sap_applies++;
         } else {
           QXD_HIP(hipMemcpyAsync(phi[k], r, bytes, hipMemcpyDeviceToDevice, s));
         }
@@ -173,7 +185,7 @@ qxd_status fgcr(qxd_handle* h, InnerOp op, qxd_nn* net, int fallback_after, VT* 
         QXD_TRY(read_scal(h, S_FB + k, 1, s));
         double b2 = h->scal_host[S_FB + k];
         if (!std::isfinite(b2) || !(b2 > 0.0)) {
-          if (use_nn) {  // the network produced a useless direction: drop it, redo the step plainly
+          if (use_nn) {  // the preconditioner produced a useless direction: drop it, redo the step plainly
             use_nn = false;
             res->fell_back = true;
             redo = true;
@@ -382,7 +394,15 @@ extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm
   if (nkv > 24) return QXD_EINVAL;
   int mode = prm->inner_prec == QXD_F64 ? 0 : prm->inner_prec == QXD_F32 ? 1 : prm->inner_prec == QXD_BF16 ? 2 : -1;
   if (mode < 0) return QXD_EINVAL;
-  if (mode == 0 && net) return QXD_EINVAL;  // the network runs on FP32 vectors
+  Precond pc;
+  pc.net = net;
+  if (prm->sap_ncy > 0) {
+    if (net || prm->sap_nmr < 1) return QXD_EINVAL;  // one preconditioner at a time
+    if (!sap_supported(h)) return QXD_EGEOM;
+    pc.sap_ncy = prm->sap_ncy;
+    pc.sap_nmr = prm->sap_nmr;
+  }
+  if (mode == 0 && pc.any()) return QXD_EINVAL;  // the preconditioners run on FP32 vectors
   hipStream_t s = as_stream(stream);
   size_t n64 = (size_t)12 * h->Ve, n32 = (size_t)6 * h->Ve;
   size_t b64 = n64 * sizeof(double2);
@@ -423,7 +443,7 @@ extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm
     if (mode == 0) {
       // plain FP64 FGCR on the current residual: D_hat e = r, to the final target
       QXD_HIP(hipMemcpyAsync(w, r, b64, hipMemcpyDeviceToDevice, s));
-      ic = fgcr<double2>(h, op, nullptr, fallback_after, e64, w, n64, nkv, 0.5 * tol, steps_left, &fr, s);
+      ic = fgcr<double2>(h, op, Precond{}, fallback_after, e64, w, n64, nkv, 0.5 * tol, steps_left, &fr, s);
       if (ic != QXD_OK) { rc = ic; break; }
       h->scal_host[S_ONE] = 1.0;
       h->scal_host[S_ONE + 1] = 0.0;
@@ -435,15 +455,16 @@ extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm
       // FP32 inner solve of D_hat e = r / |r|, then x += |r| e
       blas_down(h, r32, r, S_RR, s);
       double itol = std::fmax(inner_res, 0.5 * tol / rn);
-      ic = fgcr<float4>(h, op, net, fallback_after, e32, r32, n32, nkv, itol, steps_left, &fr, s);
+      ic = fgcr<float4>(h, op, pc, fallback_after, e32, r32, n32, nkv, itol, steps_left, &fr, s);
       if (ic != QXD_OK) { rc = ic; break; }
       blas_up_acc(h, xe, e32, S_RR, s);
     }
     st.inner_it += fr.steps;
     st.schur_applies += fr.applies;
     st.nn_applies += fr.nn_applies;
+    st.sap_applies += fr.sap_applies;
     st.fell_back |= fr.fell_back ? 1 : 0;
-    if (fr.fell_back) net = nullptr;
+    if (fr.fell_back) pc = Precond{};
     steps_left -= fr.steps;
     st.outer_it = outer + 1;
     // FP64 true residual of the Schur system
@@ -529,7 +550,7 @@ extern "C" qxd_status qxd_nn_harvest(qxd_handle* h, const void* b, int npairs, v
   };
   FgcrResult fr;
   InnerOp op{0};
-  qxd_status rc = fgcr<double2>(h, op, nullptr, 1 << 30, xe, r, n64, 4, 1e-10 * nb, 50000, &fr, s, &on_cycle);
+  qxd_status rc = fgcr<double2>(h, op, Precond{}, 1 << 30, xe, r, n64, 4, 1e-10 * nb, 50000, &fr, s, &on_cycle);
   int nsnap = (int)snaps.size() / 2;
   if (rc == QXD_OK && nsnap > 0) {
     int take = std::min(npairs, nsnap);

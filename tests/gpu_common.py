@@ -37,3 +37,17 @@ def even_only(o, psi):
     out = psi.copy()
     out[o.parity() == 1] = 0
     return out
+
+
+def half32(lat, psi):
+    """even-site spinor (V, 4, 3) -> FP32 even half field on the device"""
+    import paper_1908_11673_amd as qxd
+    return lat.pack(to_dev(psi), qxd.F32)[:12 * lat.Ve].clone()
+
+
+def from_half32(lat, t):
+    """FP32 even half field -> (V, 4, 3) complex128 spinor (odd sites zero)"""
+    import paper_1908_11673_amd as qxd
+    full = lat.field(qxd.F32, full=True)
+    full[:12 * lat.Ve] = t
+    return lat.unpack(full, qxd.F32).cpu().numpy()
