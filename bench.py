@@ -269,9 +269,10 @@ def copy_calibration(torch):
 def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False):
     """Time to a true FP64 residual 1e-10 on the benchmark lattice, one Gaussian
     source per flavour: FP64 CG against defect-correction CG and FGCR with FP32
-    and bf16-link inner solves, and FP32-inner FGCR preconditioned by a network
-    trained (per flavour) on pairs harvested from seeded 32 x 16^3 fields with
-    the same statistics."""
+    and bf16-link inner solves, FP32-inner FGCR preconditioned by SAP (one cycle,
+    8 minimal-residual steps per 4^4 block), and FP32-inner FGCR preconditioned
+    by a network trained (per flavour) on pairs harvested from seeded 32 x 16^3
+    fields with the same statistics."""
     import synthgen as sg
     from paper_1908_11673_amd import learned
     c3 = sg.WORKLOADS["c3"]
@@ -304,13 +305,14 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False):
             return lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner, check_every=8), x,
                                             bd, check=False)
 
-        def fgcr(inner, network=None):
-            return lambda: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner), network, x, bd,
-                                              check=False)
+        def fgcr(inner, network=None, sap_ncy=0, sap_nmr=8):
+            prm = qxd.solver_params(res=1e-10, inner_prec=inner, sap_ncy=sap_ncy, sap_nmr=sap_nmr)
+            return lambda: qxd.qxd_solve_fgcr(lat.h, prm, network, x, bd, check=False)
 
         legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16))]
         if not big:  # FGCR's 2 nkv direction vectors do not fit beside the 128 x 64^3 operator
-            legs += [("fgcr_f32_in_f64", fgcr(qxd.F32)), ("fgcr_bf16links_in_f64", fgcr(qxd.BF16))]
+            legs += [("fgcr_f32_in_f64", fgcr(qxd.F32)), ("fgcr_bf16links_in_f64", fgcr(qxd.BF16)),
+                     ("fgcr_f32_sap_in_f64", fgcr(qxd.F32, sap_ncy=1, sap_nmr=8))]
         if net is not None:
             legs.append(("fgcr_f32_nn_in_f64", fgcr(qxd.F32, net)))
         for tag, fn in legs:
@@ -323,7 +325,7 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False):
                 times.append((time.perf_counter() - t0) * 1e3)
             res[tag] = {"ms_median": round(float(np.median(times)), 2), "status": st["status"],
                         "iterations": st["inner_it"], "outer": st["outer_it"], "schur_applies": st["schur_applies"],
-                        "nn_applies": st["nn_applies"], "fell_back": st["fell_back"],
+                        "nn_applies": st["nn_applies"], "sap_applies": st["sap_applies"], "fell_back": st["fell_back"],
                         "true_residual": st["true_residual"]}
             log("solve %s %s: %.1f ms, %d it, res %.2e, status %d" % (name, tag, np.median(times), st["inner_it"],
                                                                        st["true_residual"], st["status"]))
