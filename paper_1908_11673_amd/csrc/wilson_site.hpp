@@ -9,10 +9,11 @@
 #pragma once
 #include "qxd_internal.hpp"
 
-// Add (1 - g_MU) W s (FWD) or (1 + g_MU) W^+ s (backward) to acc, W the link u.
+// The two pieces of a hop on either side of the colour multiplication:
+// project s onto the two-spinor (h0, h1) of (1 - g_MU) (FWD) or (1 + g_MU), and
+// add the rebuilt four-spinor of the multiplied two-spinor (w0, w1) to acc.
 template <int MU, bool FWD, class T>
-__device__ __forceinline__ void hop_term(cx<T> acc[12], const cx<T> s[12], const cx<T> u[9], bool neg) {
-  cx<T> h0[3], h1[3];
+__device__ __forceinline__ void spin_project(const cx<T> s[12], cx<T> h0[3], cx<T> h1[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const cx<T> s0 = s[a], s1 = s[3 + a], s2 = s[6 + a], s3 = s[9 + a];
@@ -30,24 +31,10 @@ __device__ __forceinline__ void hop_term(cx<T> acc[12], const cx<T> s[12], const
       h1[a] = FWD ? s1 - ti(s3) : s1 + ti(s3);
     }
   }
-  if (MU == 0 && neg) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      h0[a] = -h0[a];
-      h1[a] = -h1[a];
-    }
-  }
-  cx<T> w0[3], w1[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (FWD) {
-      w0[a] = u[3 * a] * h0[0] + u[3 * a + 1] * h0[1] + u[3 * a + 2] * h0[2];
-      w1[a] = u[3 * a] * h1[0] + u[3 * a + 1] * h1[1] + u[3 * a + 2] * h1[2];
-    } else {
-      w0[a] = cmul_conj(u[a], h0[0]) + cmul_conj(u[3 + a], h0[1]) + cmul_conj(u[6 + a], h0[2]);
-      w1[a] = cmul_conj(u[a], h1[0]) + cmul_conj(u[3 + a], h1[1]) + cmul_conj(u[6 + a], h1[2]);
-    }
-  }
+}
+
+template <int MU, bool FWD, class T>
+__device__ __forceinline__ void spin_rebuild_add(cx<T> acc[12], const cx<T> w0[3], const cx<T> w1[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     acc[a] = acc[a] + w0[a];
@@ -66,6 +53,40 @@ __device__ __forceinline__ void hop_term(cx<T> acc[12], const cx<T> s[12], const
       acc[9 + a] = FWD ? acc[9 + a] + ti(w1[a]) : acc[9 + a] - ti(w1[a]);
     }
   }
+}
+
+// w = u h (FWD) or u^+ h on both colour vectors of a two-spinor
+template <bool FWD, class T>
+__device__ __forceinline__ void colour_mul(const cx<T> u[9], const cx<T> h0[3], const cx<T> h1[3], cx<T> w0[3],
+                                           cx<T> w1[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (FWD) {
+      w0[a] = u[3 * a] * h0[0] + u[3 * a + 1] * h0[1] + u[3 * a + 2] * h0[2];
+      w1[a] = u[3 * a] * h1[0] + u[3 * a + 1] * h1[1] + u[3 * a + 2] * h1[2];
+    } else {
+      w0[a] = cmul_conj(u[a], h0[0]) + cmul_conj(u[3 + a], h0[1]) + cmul_conj(u[6 + a], h0[2]);
+      w1[a] = cmul_conj(u[a], h1[0]) + cmul_conj(u[3 + a], h1[1]) + cmul_conj(u[6 + a], h1[2]);
+    }
+  }
+}
+
+// Add (1 - g_MU) W s (FWD) or (1 + g_MU) W^+ s (backward) to acc, W the link u;
+// neg flips the sign (antiperiodic time wrap).
+template <int MU, bool FWD, class T>
+__device__ __forceinline__ void hop_term(cx<T> acc[12], const cx<T> s[12], const cx<T> u[9], bool neg) {
+  cx<T> h0[3], h1[3];
+  spin_project<MU, FWD>(s, h0, h1);
+  if (MU == 0 && neg) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      h0[a] = -h0[a];
+      h1[a] = -h1[a];
+    }
+  }
+  cx<T> w0[3], w1[3];
+  colour_mul<FWD>(u, h0, h1, w0, w1);
+  spin_rebuild_add<MU, FWD>(acc, w0, w1);
 }
 
 template <class T>
