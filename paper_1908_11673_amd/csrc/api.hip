@@ -105,6 +105,7 @@ extern "C" qxd_status qxd_trim(qxd_handle* h) {
     h->ws_bytes[i] = 0;
   }
   h->has_gauge = false;
+  h->sap_gen = 0;  // its block-order copies went with the workspaces
   return QXD_OK;
 }
 

@@ -399,5 +399,6 @@ extern "C" qxd_status qxd_clover_invert(qxd_handle* h, qxd_clover_stats* stats, 
   }
   if (res[2] != 0) return QXD_ESINGULAR;
   h->has_inverse = true;
+  ++h->setup_gen;
   return QXD_OK;
 }

@@ -87,10 +87,11 @@ __device__ inline int geo_half(const Geo& g, int x0, int x1, int x2, int x3) {
 // x1 moved by L1 on the doubled direction (period 2 L1)
 __device__ inline int geo_mirror_x1(const Geo& g, int x1) { return x1 >= g.L1 ? x1 - g.L1 : x1 + g.L1; }
 
-// Half index of the neighbour x + DIR e_MU; *neg set when the hop crosses the
-// antiperiodic time boundary.
+// Move x to its neighbour x + DIR e_MU (with C*, crossing the boundary of a
+// direction k <= cstar, k >= 2, shifts x1 by L1); *neg set when the hop crosses
+// the antiperiodic time boundary.
 template <int MU, int DIR>
-__device__ inline int geo_nb(const Geo& g, int x0, int x1, int x2, int x3, bool& neg) {
+__device__ inline void geo_step(const Geo& g, int& x0, int& x1, int& x2, int& x3, bool& neg) {
   neg = false;
   if (MU == 0) {
     x0 += DIR;
@@ -113,6 +114,12 @@ __device__ inline int geo_nb(const Geo& g, int x0, int x1, int x2, int x3, bool&
       if (g.cstar >= 3) x1 = geo_mirror_x1(g, x1);
     }
   }
+}
+
+// Half index of the neighbour x + DIR e_MU
+template <int MU, int DIR>
+__device__ inline int geo_nb(const Geo& g, int x0, int x1, int x2, int x3, bool& neg) {
+  geo_step<MU, DIR>(g, x0, x1, x2, x3, neg);
   return geo_half(g, x0, x1, x2, x3);
 }
 
@@ -320,6 +327,8 @@ struct qxd_handle {
   size_t npartial = 0;        // doubles in `partial`
   bool tchunk_env = false;    // walk chunk fixed by QXD_TILE_CHUNK
   bool stream_kernels = false; // time-streaming Schur kernels (measured slower; kept for tuning)
+  uint64_t setup_gen = 0;     // bumped whenever the links or clover blocks are rebuilt
+  uint64_t sap_gen = 0;       // setup_gen of SAP's block-order copies (0: none)
   // solver workspaces (grow-only), indexed by role
   void* ws[64] = {};
   size_t ws_bytes[64] = {};

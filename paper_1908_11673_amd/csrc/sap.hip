@@ -10,14 +10,25 @@
 // workgroup per block and no races: x is read outside the block (other colour)
 // and written inside it.  ncy cycles (colour 0 then 1) from x = 0 give M eta.
 //
+// Block layout.  The even-odd half fields keep x3 fastest, so the 256 sites of
+// a block sit in runs of two consecutive half indices, and a workgroup reading
+// them would use a fraction of every cache line it pulls.  SAP therefore works
+// on copies in block order: component k of site t (local index
+// 64 l0 + 16 l1 + 4 l2 + l3) of block B at (B * ncomp + k) * 256 + t, blocks
+// numbered colour-major (B = colour * nhalf + j, j the workgroup of that colour's
+// launch).  The links (36 float2 a site, forward links of both parities) and the
+// clover blocks (18 float4) are copied once per gauge field and flavour; the
+// iterate x and the source eta (6 float4) live in block order for the whole
+// application, and only the first and last half cycles touch the half fields.
+//
 // A workgroup of 256 threads owns one block, one thread per site; a site keeps
-// its four forward links in registers.  Each minimal-residual step every site
-// publishes rho (24.6 kB of LDS) and, for each direction, the backward hop it
-// owes its forward neighbour, (1 + g_mu) U^+ rho as two colour vectors (49.2 kB):
-// 74 kB of LDS per block, so two blocks share a CU.  The block reductions of the
-// step go through LDS.  The residual at entry
-// (the only part that reads outside the block) is a site-parallel kernel of its
-// own, run before each half cycle but the first.
+// its four forward links in registers.  Each application of D_B every site
+// publishes its spinor (24.6 kB of LDS) and, for each direction, the backward
+// hop it owes its forward neighbour, (1 + g_mu) U^+ rho as two colour vectors
+// (49.2 kB): 74 kB of LDS per block, so two blocks share a CU.  The residual at
+// entry uses the same exchange for the in-block part of D x and global loads
+// for the hops that cross the block's faces.  The block reductions of the
+// minimal-residual step go through LDS.
 #include "blas.hpp"
 #include "wilson_site.hpp"
 
@@ -28,15 +39,65 @@ constexpr int kSapSites = kSapB * kSapB * kSapB * kSapB;  // 256: one thread per
 
 struct SapGeo {
   int nb1, nb2, nb3;  // blocks along x1, x2, x3 (nb3 even)
+  int nhalf;          // blocks of one colour
 };
 
+// Block-order index B * 256 + t of the site x.
+__device__ __forceinline__ int sap_bsite(const SapGeo& sb, int x0, int x1, int x2, int x3) {
+  const int c0 = x0 >> 2, c1 = x1 >> 2, c2 = x2 >> 2, c3 = x3 >> 2;
+  const int j = ((c0 * sb.nb1 + c1) * sb.nb2 + c2) * (sb.nb3 >> 1) + (c3 >> 1);
+  const int B = ((c0 + c1 + c2 + c3) & 1) * sb.nhalf + j;
+  return B * kSapSites + (((x0 & 3) << 6) | ((x1 & 3) << 4) | ((x2 & 3) << 2) | (x3 & 3));
+}
+
+// Coordinates of block j of the given colour: along x3 the colours alternate.
+__device__ __forceinline__ void sap_block_coords(const SapGeo& sb, int colour, int j, int& c0, int& c1, int& c2,
+                                                 int& c3) {
+  const int half3 = sb.nb3 >> 1;
+  const int k3 = j % half3;
+  int line = j / half3;
+  c2 = line % sb.nb2;
+  line /= sb.nb2;
+  c1 = line % sb.nb1;
+  c0 = line / sb.nb1;
+  c3 = 2 * k3 + ((c0 + c1 + c2 + colour) & 1);
+}
+
+template <int NC, class T>
+__device__ __forceinline__ T* sap_blk(T* base, int B) {
+  return base + (size_t)B * NC * kSapSites;
+}
+
+// Block-order copies of the links and the clover blocks (one thread per site).
+__global__ __launch_bounds__(kSapSites) void k_sap_pack(Geo g, SapGeo sb, const float2* __restrict__ V32,
+                                                        const float4* __restrict__ He,
+                                                        const float4* __restrict__ Ho, float2* __restrict__ Vb,
+                                                        float4* __restrict__ Cb) {
+  const int B = blockIdx.x, colour = B >= sb.nhalf ? 1 : 0;
+  int c0, c1, c2, c3;
+  sap_block_coords(sb, colour, B - colour * sb.nhalf, c0, c1, c2, c3);
+  const int t = threadIdx.x;
+  const int x0 = kSapB * c0 + (t >> 6), x1 = kSapB * c1 + ((t >> 4) & 3), x2 = kSapB * c2 + ((t >> 2) & 3),
+            x3 = kSapB * c3 + (t & 3);
+  const int p = (x0 + x1 + x2 + x3) & 1;
+  const size_t Ve = g.Ve, h = geo_half(g, x0, x1, x2, x3);
+  const float2* Vp = V32 + (size_t)p * 36 * Ve;
+  const float4* Hp = p ? Ho : He;
+  float2* vb = sap_blk<36>(Vb, B);
+  float4* cb = sap_blk<18>(Cb, B);
+#pragma unroll 4
+  for (int k = 0; k < 36; ++k) vb[k * kSapSites + t] = Vp[k * Ve + h];
+#pragma unroll 6
+  for (int k = 0; k < 18; ++k) cb[k * kSapSites + t] = Hp[k * Ve + h];
+}
+
 // Plain (cached) loads: every step of a block solve reads the clover blocks again.
-__device__ __forceinline__ void sap_clover(const float4* __restrict__ C, size_t Ve, int h, const cx<float> in[12],
+__device__ __forceinline__ void sap_clover(const float4* __restrict__ cb, int t, const cx<float> in[12],
                                            cx<float> out[12]) {
   float r[72];
 #pragma unroll
   for (int k = 0; k < 18; ++k) {
-    float4 v = C[k * Ve + h];
+    float4 v = cb[k * kSapSites + t];
     r[4 * k] = v.x;
     r[4 * k + 1] = v.y;
     r[4 * k + 2] = v.z;
@@ -90,128 +151,160 @@ __device__ __forceinline__ void sap_recv(const float4 (*rho_s)[kSapSites], const
   }
 }
 
+// The hop along MU that leaves the block at site x (local coordinate l along
+// MU): forward from the face l = 3 with the site's own link u, backward from
+// the face l = 0 with the neighbour's link; the neighbour's x in block order.
+template <int MU>
+__device__ __forceinline__ void sap_face(const Geo& g, const SapGeo& sb, int x0, int x1, int x2, int x3, int l,
+                                         const float4* __restrict__ Xb, const float2* __restrict__ Vb,
+                                         const cx<float> u[9], cx<float> acc[12]) {
+  bool neg;
+  cx<float> s[12];
+  if (l == kSapB - 1) {
+    geo_step<MU, +1>(g, x0, x1, x2, x3, neg);
+    const int bs = sap_bsite(sb, x0, x1, x2, x3);
+    sp_load(sap_blk<6>(Xb, bs >> 8), kSapSites, bs & 255, s);
+    hop_term<MU, true>(acc, s, u, neg);
+  } else if (l == 0) {
+    geo_step<MU, -1>(g, x0, x1, x2, x3, neg);
+    const int bs = sap_bsite(sb, x0, x1, x2, x3);
+    sp_load(sap_blk<6>(Xb, bs >> 8), kSapSites, bs & 255, s);
+    cx<float> v[9];
+    const float2* vb = sap_blk<36>(Vb, bs >> 8) + MU * 9 * kSapSites + (bs & 255);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float2 w = vb[k * kSapSites];
+      v[k] = mk(w.x, w.y);
+    }
+    hop_term<MU, false>(acc, s, v, neg);
+  }
+}
+
 __device__ __forceinline__ float sap_wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
 
-// Residual of the blocks of `colour`: r = eta - D x at their sites (one
-// workgroup per block, one thread per site, the same site order as the block
-// solver), into the FP32 half fields r_e, r_o.  A site-parallel kernel of its
-// own, so that the neighbour loads of D run at full occupancy.
-__global__ __launch_bounds__(kSapSites) void k_sap_resid(Geo g, SapGeo sb, int colour,
-                                                         const float4* __restrict__ eta_e,
-                                                         const float4* __restrict__ x_e,
-                                                         const float4* __restrict__ x_o,
-                                                         const float2* __restrict__ V32,
-                                                         const float4* __restrict__ He,
-                                                         const float4* __restrict__ Ho, float4* __restrict__ r_e,
-                                                         float4* __restrict__ r_o) {
-  const int half3 = sb.nb3 >> 1;
-  int k3 = blockIdx.x % half3, line = blockIdx.x / half3;
-  const int c2 = line % sb.nb2;
-  line /= sb.nb2;
-  const int c1 = line % sb.nb1, c0 = line / sb.nb1;
-  const int c3 = 2 * k3 + ((c0 + c1 + c2 + colour) & 1);
-  const int t = threadIdx.x;
-  const int x0 = kSapB * c0 + (t >> 6), x1 = kSapB * c1 + ((t >> 4) & 3), x2 = kSapB * c2 + ((t >> 2) & 3),
-            x3 = kSapB * c3 + (t & 3);
-  const int p = (x0 + x1 + x2 + x3) & 1;
-  const int h = geo_half(g, x0, x1, x2, x3);
-  const size_t Ve = g.Ve;
-  const float2* Vp = V32 + (size_t)p * 36 * Ve;
-  const float2* Vq = V32 + (size_t)(1 - p) * 36 * Ve;
-  cx<float> r[12], xs[12], hx[12], dx[12];
-  if (p == 0) {
-    sp_load(eta_e, Ve, h, r);
-  } else {
+struct SapLds {
+  float4 rho[6][kSapSites];
+  float2 bw[4][6][kSapSites];
+  float red[3][kSapSites / 64];
+};
+
+// acc = the in-block hops of f at site t: f and the backward hops are exchanged
+// through LDS (every earlier read of the exchange buffers has passed a barrier
+// before the call).
+__device__ __forceinline__ void sap_inblock(SapLds& L, int t, int l0, int l1, int l2, int l3, const cx<float> f[12],
+                                            const cx<float> (*U)[9], cx<float> acc[12]) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) r[c] = mk(0.f, 0.f);
-  }
-  sp_load(p ? x_o : x_e, Ve, h, xs);
-  hop_site<false, float>(g, p, h, p ? x_e : x_o, Vp, Vq, hx);
-  clover_mul<float>(p ? Ho : He, Ve, h, xs, dx);
+  for (int j = 0; j < 6; ++j) L.rho[j][t] = make_float4(f[2 * j].re, f[2 * j].im, f[2 * j + 1].re, f[2 * j + 1].im);
+  if (l0 < kSapB - 1) sap_send<0>(L.bw, t, f, U[0]);
+  if (l1 < kSapB - 1) sap_send<1>(L.bw, t, f, U[1]);
+  if (l2 < kSapB - 1) sap_send<2>(L.bw, t, f, U[2]);
+  if (l3 < kSapB - 1) sap_send<3>(L.bw, t, f, U[3]);
+  __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 12; ++c) r[c] = r[c] - (dx[c] - 0.5f * hx[c]);
-  sp_store(p ? r_o : r_e, Ve, h, r);
+  for (int c = 0; c < 12; ++c) acc[c] = mk(0.f, 0.f);
+  sap_recv<0>(L.rho, L.bw, t, l0, U[0], acc);
+  sap_recv<1>(L.rho, L.bw, t, l1, U[1], acc);
+  sap_recv<2>(L.rho, L.bw, t, l2, U[2], acc);
+  sap_recv<3>(L.rho, L.bw, t, l3, U[3], acc);
 }
 
-// One half cycle on the blocks of `colour`: block solves of the residual
-// (r_e, r_o) added to x = (x_e, x_o), FP32 half fields.  XZERO: x is zero on
-// entry (first half cycle) and the residual is the source, r_e = eta (its odd
-// half is zero and r_o is not read).
-template <bool XZERO>
+enum { SAP_FIRST = 0, SAP_MID = 1, SAP_LAST = 2 };
+
+// One half cycle on the blocks of `colour` (j = blockIdx.x; its partner is block
+// j of the other colour, the other block of the pair {2 k3, 2 k3 + 1} along x3).
+//   SAP_FIRST: x = 0 on entry, so r = eta, read from the even half field eta_e;
+//              also writes the block-order eta of the block and of its partner
+//              (even sites) and zeroes the partner's x;
+//   SAP_MID:   r = eta - D x from the block-order fields;
+//   SAP_LAST:  as SAP_MID, then writes the even sites of the block's x and of
+//              its partner's (final after this half cycle) to out_e.
+template <int MODE>
 __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int colour, int nmr,
-                                                           const float4* __restrict__ r_e,
-                                                           const float4* __restrict__ r_o,
-                                                           float4* __restrict__ x_e, float4* __restrict__ x_o,
-                                                           const float2* __restrict__ V32,
-                                                           const float4* __restrict__ He,
-                                                           const float4* __restrict__ Ho) {
-  __shared__ float4 rho_s[6][kSapSites];
-  __shared__ float2 bw_s[4][6][kSapSites];
-  __shared__ float red_s[3][kSapSites / 64];
-  // the blockIdx-th block of this colour: along x3 the colours alternate
-  const int half3 = sb.nb3 >> 1;
-  int k3 = blockIdx.x % half3, line = blockIdx.x / half3;
-  const int c2 = line % sb.nb2;
-  line /= sb.nb2;
-  const int c1 = line % sb.nb1, c0 = line / sb.nb1;
-  const int c3 = 2 * k3 + ((c0 + c1 + c2 + colour) & 1);
+                                                           const float4* __restrict__ eta_e,
+                                                           float4* __restrict__ Eb, float4* __restrict__ Xb,
+                                                           const float2* __restrict__ Vb,
+                                                           const float4* __restrict__ Cb,
+                                                           float4* __restrict__ out_e) {
+  __shared__ SapLds L;
+  const int j = blockIdx.x;
+  int c0, c1, c2, c3;
+  sap_block_coords(sb, colour, j, c0, c1, c2, c3);
+  const int B = colour * sb.nhalf + j, Bp = (1 - colour) * sb.nhalf + j;
   const int t = threadIdx.x;
   const int l0 = t >> 6, l1 = (t >> 4) & 3, l2 = (t >> 2) & 3, l3 = t & 3;
   const int x0 = kSapB * c0 + l0, x1 = kSapB * c1 + l1, x2 = kSapB * c2 + l2, x3 = kSapB * c3 + l3;
   const int p = (x0 + x1 + x2 + x3) & 1;
-  const int h = geo_half(g, x0, x1, x2, x3);
+  // the partner's site with the same local index (same parity: x3 moves by 4)
+  const int x3p = x3 + ((c3 & 1) ? -kSapB : kSapB);
   const size_t Ve = g.Ve;
-  const float2* Vp = V32 + (size_t)p * 36 * Ve;
-  const float4* Hp = p ? Ho : He;
-  float4* xp = p ? x_o : x_e;
+  const float4* cb = sap_blk<18>(Cb, B);
+  float4* xb = sap_blk<6>(Xb, B);
+  float4* eb = sap_blk<6>(Eb, B);
 
   // the site's four forward links stay in registers for the whole solve
   cx<float> U[4][9];
+  {
+    const float2* vb = sap_blk<36>(Vb, B) + t;
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu)
+    for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      float2 v = Vp[(mu * 9 + k) * Ve + h];
-      U[mu][k] = mk(v.x, v.y);
-    }
-  // the block's residual: eta itself while x = 0 (r_e = eta, r_o unused),
-  // else from k_sap_resid
-  cx<float> rho[12];
-  if (p == 0 || !XZERO) {
-    sp_load(p ? r_o : r_e, Ve, h, rho);
-  } else {
-#pragma unroll
-    for (int c = 0; c < 12; ++c) rho[c] = mk(0.f, 0.f);
+      for (int k = 0; k < 9; ++k) {
+        float2 v = vb[(mu * 9 + k) * kSapSites];
+        U[mu][k] = mk(v.x, v.y);
+      }
   }
+  cx<float> rho[12];
+  if (MODE == SAP_FIRST) {
+    if (p == 0) {
+      sp_load(eta_e, Ve, geo_half(g, x0, x1, x2, x3), rho);
+      sp_store(eb, kSapSites, t, rho);
+      cx<float> ep[12];
+      sp_load(eta_e, Ve, geo_half(g, x0, x1, x2, x3p), ep);
+      sp_store(sap_blk<6>(Eb, Bp), kSapSites, t, ep);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) rho[c] = mk(0.f, 0.f);
+    }
+    cx<float> z[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) z[c] = mk(0.f, 0.f);
+    sp_store(sap_blk<6>(Xb, Bp), kSapSites, t, z);
+  } else {
+    // r = eta - D x = eta - H x + (1/2) (in-block hops + hops across the faces)
+    cx<float> xs[12], acc[12];
+    sp_load(xb, kSapSites, t, xs);
+    sap_inblock(L, t, l0, l1, l2, l3, xs, U, acc);
+    sap_face<0>(g, sb, x0, x1, x2, x3, l0, Xb, Vb, U[0], acc);
+    sap_face<1>(g, sb, x0, x1, x2, x3, l1, Xb, Vb, U[1], acc);
+    sap_face<2>(g, sb, x0, x1, x2, x3, l2, Xb, Vb, U[2], acc);
+    sap_face<3>(g, sb, x0, x1, x2, x3, l3, Xb, Vb, U[3], acc);
+    cx<float> hx[12];
+    sap_clover(cb, t, xs, hx);
+    if (p == 0) {
+      sp_load(eb, kSapSites, t, rho);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) rho[c] = mk(0.f, 0.f);
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rho[c] = rho[c] - (hx[c] - 0.5f * acc[c]);
+    __syncthreads();  // the exchange buffers are published again below
+  }
+
   cx<float> e[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) e[c] = mk(0.f, 0.f);
   const int wave = t >> 6, lane = t & 63;
   for (int step = 0; step < nmr; ++step) {
-    // publish rho and the backward hops this site owes its forward neighbours
-    // (every read of the previous step's values came before its reduction barrier)
-#pragma unroll
-    for (int j = 0; j < 6; ++j)
-      rho_s[j][t] = make_float4(rho[2 * j].re, rho[2 * j].im, rho[2 * j + 1].re, rho[2 * j + 1].im);
-    if (l0 < kSapB - 1) sap_send<0>(bw_s, t, rho, U[0]);
-    if (l1 < kSapB - 1) sap_send<1>(bw_s, t, rho, U[1]);
-    if (l2 < kSapB - 1) sap_send<2>(bw_s, t, rho, U[2]);
-    if (l3 < kSapB - 1) sap_send<3>(bw_s, t, rho, U[3]);
-    __syncthreads();
-    // v = D_B rho = H rho - (1/2) (in-block hops)
-    cx<float> acc[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = mk(0.f, 0.f);
-    sap_recv<0>(rho_s, bw_s, t, l0, U[0], acc);
-    sap_recv<1>(rho_s, bw_s, t, l1, U[1], acc);
-    sap_recv<2>(rho_s, bw_s, t, l2, U[2], acc);
-    sap_recv<3>(rho_s, bw_s, t, l3, U[3], acc);
-    cx<float> v[12];
-    sap_clover(Hp, Ve, h, rho, v);
+    // v = D_B rho = H rho - (1/2) (in-block hops); every read of the previous
+    // step's exchange buffers came before its reduction barrier
+    cx<float> acc[12], v[12];
+    sap_inblock(L, t, l0, l1, l2, l3, rho, U, acc);
+    sap_clover(cb, t, rho, v);
     float are = 0.f, aim = 0.f, nn = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
@@ -225,17 +318,17 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
     aim = sap_wave_sum(aim);
     nn = sap_wave_sum(nn);
     if (lane == 0) {
-      red_s[0][wave] = are;
-      red_s[1][wave] = aim;
-      red_s[2][wave] = nn;
+      L.red[0][wave] = are;
+      L.red[1][wave] = aim;
+      L.red[2][wave] = nn;
     }
     __syncthreads();
     are = aim = nn = 0.f;
 #pragma unroll
     for (int w = 0; w < kSapSites / 64; ++w) {
-      are += red_s[0][w];
-      aim += red_s[1][w];
-      nn += red_s[2][w];
+      are += L.red[0][w];
+      aim += L.red[1][w];
+      nn += L.red[2][w];
     }
     // alpha = (v, rho) / (v, v); a block whose residual vanished stays put
     const cx<float> alpha = nn > 0.f ? mk(are / nn, aim / nn) : mk(0.f, 0.f);
@@ -245,16 +338,24 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
       rho[c] = rho[c] - alpha * v[c];
     }
   }
-  if (!XZERO) {
+  if (MODE != SAP_FIRST) {
     cx<float> xs[12];
-    sp_load(xp, Ve, h, xs);
+    sp_load(xb, kSapSites, t, xs);
 #pragma unroll
     for (int c = 0; c < 12; ++c) e[c] = e[c] + xs[c];
   }
-  sp_store(xp, Ve, h, e);
+  sp_store(xb, kSapSites, t, e);
+  if (MODE == SAP_LAST && p == 0) {
+    sp_store(out_e, Ve, geo_half(g, x0, x1, x2, x3), e);
+    cx<float> xp[12];
+    sp_load(sap_blk<6>(Xb, Bp), kSapSites, t, xp);
+    sp_store(out_e, Ve, geo_half(g, x0, x1, x2, x3p), xp);
+  }
 }
 
-enum { W_SAP_XO = 13, W_SAP_RE, W_SAP_RO };  // workspace roles (free in the solvers' table)
+// workspace roles (free in the solvers' table): block-order links, clover
+// blocks, iterate and source
+enum { W_SAP_VB = 8, W_SAP_CB = 9, W_SAP_XB = 13, W_SAP_EB = 14 };
 
 }  // namespace
 
@@ -272,30 +373,30 @@ qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, float4* out_e, co
   if (ncy < 1 || nmr < 1 || ncy > 64 || nmr > 64) return QXD_EINVAL;
   if (!h->has_inverse) return QXD_ESTATE;
   if (!sap_supported(h)) return QXD_EGEOM;
-  const size_t n32 = (size_t)6 * h->Ve;
-  float4* xo = (float4*)ws_get(h, W_SAP_XO, n32 * sizeof(float4));
-  float4* re = (float4*)ws_get(h, W_SAP_RE, n32 * sizeof(float4));
-  float4* ro = (float4*)ws_get(h, W_SAP_RO, n32 * sizeof(float4));
-  if (!xo || !re || !ro) return QXD_ENOMEM;
-  // x = 0 on both halves: the first half cycle writes the colour-0 blocks only
-  blas_zero<float4>(out_e, n32, s);
-  blas_zero<float4>(xo, n32, s);
-  SapGeo sb{h->geo.Le1 / kSapB, h->geo.Le2 / kSapB, h->geo.Le3 / kSapB};
-  const int nblk = (h->geo.Le0 / kSapB) * sb.nb1 * sb.nb2 * sb.nb3;
-  dim3 grid(nblk / 2), blk(kSapSites);
-  const float2* V32 = reinterpret_cast<const float2*>(h->V32);
-  const float4* He = reinterpret_cast<const float4*>(h->He32);
-  const float4* Ho = reinterpret_cast<const float4*>(h->Ho32);
+  const size_t V = (size_t)h->V;
+  float2* Vb = (float2*)ws_get(h, W_SAP_VB, V * 36 * sizeof(float2));
+  float4* Cb = (float4*)ws_get(h, W_SAP_CB, V * 18 * sizeof(float4));
+  float4* Xb = (float4*)ws_get(h, W_SAP_XB, V * 6 * sizeof(float4));
+  float4* Eb = (float4*)ws_get(h, W_SAP_EB, V * 6 * sizeof(float4));
+  if (!Vb || !Cb || !Xb || !Eb) return QXD_ENOMEM;
+  const Geo& g = h->geo;
+  const int nblk = (g.Le0 / kSapB) * (g.Le1 / kSapB) * (g.Le2 / kSapB) * (g.Le3 / kSapB);
+  const SapGeo sb{g.Le1 / kSapB, g.Le2 / kSapB, g.Le3 / kSapB, nblk / 2};
+  if (h->sap_gen != h->setup_gen) {  // links or clover changed since the last copy
+    hipLaunchKernelGGL(k_sap_pack, dim3(nblk), dim3(kSapSites), 0, s, g, sb, reinterpret_cast<const float2*>(h->V32),
+                       reinterpret_cast<const float4*>(h->He32), reinterpret_cast<const float4*>(h->Ho32), Vb, Cb);
+    QXD_HIP(hipGetLastError());
+    h->sap_gen = h->setup_gen;
+  }
+  const dim3 grid(sb.nhalf), blk(kSapSites);
   for (int cy = 0; cy < ncy; ++cy)
     for (int colour = 0; colour < 2; ++colour) {
-      if (cy == 0 && colour == 0) {
-        hipLaunchKernelGGL(k_sap_half<true>, grid, blk, 0, s, h->geo, sb, colour, nmr, in_e, nullptr, out_e, xo, V32,
-                           He, Ho);
-      } else {
-        hipLaunchKernelGGL(k_sap_resid, grid, blk, 0, s, h->geo, sb, colour, in_e, out_e, xo, V32, He, Ho, re, ro);
-        hipLaunchKernelGGL(k_sap_half<false>, grid, blk, 0, s, h->geo, sb, colour, nmr, re, ro, out_e, xo, V32, He,
-                           Ho);
-      }
+      if (cy == 0 && colour == 0)
+        hipLaunchKernelGGL(k_sap_half<SAP_FIRST>, grid, blk, 0, s, g, sb, colour, nmr, in_e, Eb, Xb, Vb, Cb, out_e);
+      else if (cy == ncy - 1 && colour == 1)
+        hipLaunchKernelGGL(k_sap_half<SAP_LAST>, grid, blk, 0, s, g, sb, colour, nmr, in_e, Eb, Xb, Vb, Cb, out_e);
+      else
+        hipLaunchKernelGGL(k_sap_half<SAP_MID>, grid, blk, 0, s, g, sb, colour, nmr, in_e, Eb, Xb, Vb, Cb, out_e);
     }
   QXD_HIP(hipGetLastError());
   return QXD_OK;

@@ -19,7 +19,7 @@ using clk = std::chrono::steady_clock;
 // workspace roles
 enum {
   W_BH = 0, W_XE, W_R, W_P, W_Z, W_W, W_FULL0, W_FULL1,  // FP64 halves (FULL*: full fields)
-  W_R32 = 10, W_E32, W_E64,  // 13: the SAP iterate's odd half (sap.hip)
+  W_R32 = 10, W_E32, W_E64,  // 8, 9, 13, 14: SAP's block-order fields (sap.hip)
   W_PHI = 16,    // 16..(16+QXD_MAXKV-1)
   W_CHI = 40     // 40..(40+QXD_MAXKV-1) -> needs ws[] of 64+: keep nkv <= 24
 };
