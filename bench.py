@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--nn-fields", type=int, default=10, help="fields for the network training (0: no network)")
     ap.add_argument("--nn-epochs", type=int, default=8)
+    ap.add_argument("--legs", default="", help="comma-separated solve legs to run (default: all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU path (time-slab halo exchange over xGMI) "
@@ -208,8 +209,10 @@ def main():
     if not args.no_solve:
         del ins, outs
         torch.cuda.empty_cache()
-        result["time_to_solution"] = solve_leg(qxd, torch, lats, w, flavours, 0 if big else args.nn_fields,
-                                               args.nn_epochs, big)
+        only = tuple(t for t in args.legs.split(",") if t)
+        train = not big and (not only or "fgcr_f32_nn_in_f64" in only)
+        result["time_to_solution"] = solve_leg(qxd, torch, lats, w, flavours, args.nn_fields if train else 0,
+                                               args.nn_epochs, big, only)
 
     if not args.no_cpu_baseline and not big:  # the oracle would hold 60 GB of host fields at 128 x 64^3
         log("cpu baseline (oracle) ...")
@@ -266,11 +269,14 @@ def copy_calibration(torch):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
-def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False):
+SAP_NCY, SAP_NMR = 2, 8  # fastest of a sweep over (cycles, steps) at 64 x 32^3
+
+
+def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, only=()):
     """Time to a true FP64 residual 1e-10 on the benchmark lattice, one Gaussian
     source per flavour: FP64 CG against defect-correction CG and FGCR with FP32
-    and bf16-link inner solves, FP32-inner FGCR preconditioned by SAP (one cycle,
-    8 minimal-residual steps per 4^4 block), and FP32-inner FGCR preconditioned
+    and bf16-link inner solves, FP32-inner FGCR preconditioned by SAP (two
+    cycles, 8 minimal-residual steps per 4^4 block), and FP32-inner FGCR preconditioned
     by a network trained (per flavour) on pairs harvested from seeded 32 x 16^3
     fields with the same statistics."""
     import synthgen as sg
@@ -312,10 +318,12 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False):
         legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16))]
         if not big:  # FGCR's 2 nkv direction vectors do not fit beside the 128 x 64^3 operator
             legs += [("fgcr_f32_in_f64", fgcr(qxd.F32)), ("fgcr_bf16links_in_f64", fgcr(qxd.BF16)),
-                     ("fgcr_f32_sap_in_f64", fgcr(qxd.F32, sap_ncy=1, sap_nmr=8))]
+                     ("fgcr_f32_sap_in_f64", fgcr(qxd.F32, sap_ncy=SAP_NCY, sap_nmr=SAP_NMR))]
         if net is not None:
             legs.append(("fgcr_f32_nn_in_f64", fgcr(qxd.F32, net)))
         for tag, fn in legs:
+            if only and tag not in only:
+                continue
             times = []
             for rep in range(1 if big else 3):
                 torch.cuda.synchronize()
