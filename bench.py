@@ -269,14 +269,19 @@ def copy_calibration(torch):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
-SAP_NCY, SAP_NMR = 2, 8  # fastest of a sweep over (cycles, steps) at 64 x 32^3
+# SAP in the solve leg: plain minimal-residual block solves, two cycles of 8
+# steps, the fastest of a sweep at 64 x 32^3.  The even-odd preconditioned block
+# solver (the paper's) needs fewer FGCR steps but costs twice as much per step
+# here (half the wavefronts wait in each of its two hop exchanges): 153 ms
+# against 128 ms at its best setting.
+SAP_NCY, SAP_NMR, SAP_PLAIN = 2, 8, 1
 
 
 def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, only=()):
     """Time to a true FP64 residual 1e-10 on the benchmark lattice, one Gaussian
     source per flavour: FP64 CG against defect-correction CG and FGCR with FP32
     and bf16-link inner solves, FP32-inner FGCR preconditioned by SAP (two
-    cycles, 8 minimal-residual steps per 4^4 block), and FP32-inner FGCR preconditioned
+    cycles, 8 plain minimal-residual steps per 4^4 block), and FP32-inner FGCR preconditioned
     by a network trained (per flavour) on pairs harvested from seeded 32 x 16^3
     fields with the same statistics."""
     import synthgen as sg
@@ -311,14 +316,15 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, on
             return lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner, check_every=8), x,
                                             bd, check=False)
 
-        def fgcr(inner, network=None, sap_ncy=0, sap_nmr=8):
-            prm = qxd.solver_params(res=1e-10, inner_prec=inner, sap_ncy=sap_ncy, sap_nmr=sap_nmr)
+        def fgcr(inner, network=None, sap_ncy=0, sap_nmr=8, sap_plain=0):
+            prm = qxd.solver_params(res=1e-10, inner_prec=inner, sap_ncy=sap_ncy, sap_nmr=sap_nmr,
+                                    sap_plain=sap_plain)
             return lambda: qxd.qxd_solve_fgcr(lat.h, prm, network, x, bd, check=False)
 
         legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16))]
         if not big:  # FGCR's 2 nkv direction vectors do not fit beside the 128 x 64^3 operator
             legs += [("fgcr_f32_in_f64", fgcr(qxd.F32)), ("fgcr_bf16links_in_f64", fgcr(qxd.BF16)),
-                     ("fgcr_f32_sap_in_f64", fgcr(qxd.F32, sap_ncy=SAP_NCY, sap_nmr=SAP_NMR))]
+                     ("fgcr_f32_sap_in_f64", fgcr(qxd.F32, sap_ncy=SAP_NCY, sap_nmr=SAP_NMR, sap_plain=SAP_PLAIN))]
         if net is not None:
             legs.append(("fgcr_f32_nn_in_f64", fgcr(qxd.F32, net)))
         for tag, fn in legs:

@@ -104,6 +104,7 @@ typedef struct {
   int fallback_after;  /* NN FGCR: inner steps without progress before dropping M */
   int sap_ncy;         /* FGCR: > 0 selects the SAP preconditioner with this many cycles (net must be NULL) */
   int sap_nmr;         /* SAP: minimal-residual steps per block solve */
+  int sap_plain;       /* SAP: 0 (default) even-odd preconditioned block solves, 1 plain (see qxd_sap_apply) */
 } qxd_solver_params;
 
 typedef struct {
@@ -212,14 +213,20 @@ qxd_status qxd_solve_fgcr(qxd_handle *h, const qxd_solver_params *params, qxd_nn
  * ncy cycles of SAP on the full operator D in FP32 from x = 0.  The extended
  * lattice is cut into 4^4 blocks coloured by the parity of their block
  * coordinates; a cycle visits colour 0 then colour 1 and, on every block of
- * that colour, takes the residual r = eta - D x, runs nmr minimal-residual
- * steps on D restricted to the block (hops leaving it dropped) and adds the
- * block solution to x.  (Exact block elimination would make out_e = D_hat^-1
- * in_e.)  in_e, out_e: FP32 even half fields (device, distinct).  QXD_EGEOM
- * unless every extended extent is a multiple of 8 and, with C* in k >= 2, L1 is
- * a multiple of 8; QXD_EINVAL for ncy or nmr outside 1..64; QXD_ESTATE before
- * the clover inverse.  Also the FGCR preconditioner (qxd_solver_params.sap_ncy). */
-qxd_status qxd_sap_apply(qxd_handle *h, int ncy, int nmr, void *out_e, const void *in_e, void *stream);
+ * that colour, takes the residual r = eta - D x, solves D_B e = r_B
+ * approximately, D_B being D restricted to the block (hops leaving it
+ * dropped), and adds e to x.  The block solve is nmr minimal-residual steps
+ * from e = 0: with eo = 1 (the paper's choice) on the block's even-odd Schur
+ * complement H_ee - D_eo H_oo^-1 D_oe with source r_e - D_eo H_oo^-1 r_o, then
+ * e_o = H_oo^-1 (r_o - D_oe e_e); with eo = 0 on D_B itself.  (Exact block
+ * elimination would make out_e = D_hat^-1 in_e.)  in_e, out_e: FP32 even half
+ * fields (device, distinct).  The library keeps block-ordered copies of the
+ * links and clover blocks (about 680 bytes a site of the extended lattice)
+ * until qxd_trim or qxd_destroy.  QXD_EGEOM unless every extended extent is a
+ * multiple of 8 and, with C* in k >= 2, L1 is a multiple of 8; QXD_EINVAL for
+ * ncy or nmr outside 1..64 or eo not 0 or 1; QXD_ESTATE before the clover
+ * inverse.  Also the FGCR preconditioner (qxd_solver_params.sap_ncy). */
+qxd_status qxd_sap_apply(qxd_handle *h, int ncy, int nmr, int eo, void *out_e, const void *in_e, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Learned preconditioner: three 3^4-tap convolutions on the extended lattice

@@ -51,7 +51,7 @@ class qxd_solver_params(ctypes.Structure):
     _fields_ = [("nmx", ctypes.c_int), ("res", ctypes.c_double), ("inner_prec", ctypes.c_int),
                 ("inner_res", ctypes.c_double), ("nkv", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("fallback_after", ctypes.c_int), ("sap_ncy", ctypes.c_int),
-                ("sap_nmr", ctypes.c_int)]
+                ("sap_nmr", ctypes.c_int), ("sap_plain", ctypes.c_int)]
 
 
 class qxd_solver_stats(ctypes.Structure):
@@ -102,7 +102,7 @@ _SIGNATURES = {
     "qxd_nn_set_skip": ([_P, _D], _I),
     "qxd_nn_get_weights": ([_P, _P], _I),
     "qxd_nn_apply": ([_P, _P, _P, _P, _P], _I),
-    "qxd_sap_apply": ([_P, _I, _I, _P, _P, _P], _I),
+    "qxd_sap_apply": ([_P, _I, _I, _I, _P, _P, _P], _I),
     "qxd_nn_loss_grad": ([_P, _P, _P, _P, _I, _I, ctypes.POINTER(_D), _P, _P], _I),
     "qxd_nn_harvest": ([_P, _P, _I, _P, _P, ctypes.POINTER(_I), _P], _I),
     "qxd_nn_train": ([_P, _P, ctypes.POINTER(qxd_train_params), _P, _P, _I, ctypes.POINTER(qxd_train_stats), _P],
@@ -236,9 +236,9 @@ def qxd_unpack(h, prec, aos, soa, stream=None):
 
 
 def solver_params(nmx=100000, res=1e-10, inner_prec=F32, inner_res=1e-5, nkv=16, max_outer=100, check_every=4,
-                  fallback_after=50, sap_ncy=0, sap_nmr=4):
+                  fallback_after=50, sap_ncy=0, sap_nmr=4, sap_plain=0):
     return qxd_solver_params(int(nmx), float(res), int(inner_prec), float(inner_res), int(nkv), int(max_outer),
-                             int(check_every), int(fallback_after), int(sap_ncy), int(sap_nmr))
+                             int(check_every), int(fallback_after), int(sap_ncy), int(sap_nmr), int(sap_plain))
 
 
 def qxd_solve_cg(h, params, x, b, stream=None, check=True):
@@ -288,8 +288,9 @@ def qxd_nn_get_weights(net):
     return w
 
 
-def qxd_sap_apply(h, ncy, nmr, out_e, in_e, stream=None):
-    _check(load().qxd_sap_apply(h, int(ncy), int(nmr), _ptr(out_e), _ptr(in_e), _stream(stream)), "qxd_sap_apply")
+def qxd_sap_apply(h, ncy, nmr, eo, out_e, in_e, stream=None):
+    _check(load().qxd_sap_apply(h, int(ncy), int(nmr), int(eo), _ptr(out_e), _ptr(in_e), _stream(stream)),
+           "qxd_sap_apply")
 
 
 def qxd_nn_apply(h, net, out_e, in_e, stream=None):

@@ -328,7 +328,7 @@ struct qxd_handle {
   bool tchunk_env = false;    // walk chunk fixed by QXD_TILE_CHUNK
   bool stream_kernels = false; // time-streaming Schur kernels (measured slower; kept for tuning)
   uint64_t setup_gen = 0;     // bumped whenever the links or clover blocks are rebuilt
-  uint64_t sap_gen = 0;       // setup_gen of SAP's block-order copies (0: none)
+  uint64_t sap_gen = 0;       // SAP's block-order copies: 2 setup_gen + slot order (0: none)
   // solver workspaces (grow-only), indexed by role
   void* ws[64] = {};
   size_t ws_bytes[64] = {};
@@ -387,6 +387,7 @@ qxd_status qxd_schur_apply(qxd_handle* h, qxd_prec p, int dagger, void* out_e, c
 qxd_status nn_apply_internal(qxd_handle* h, qxd_nn* net, float4* out_e, const float4* in_e, hipStream_t s);
 // SAP preconditioner of the Schur system (sap.hip): out_e = (M_SAP (in_e, 0))_e
 bool sap_supported(const qxd_handle* h);
-qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, float4* out_e, const float4* in_e, hipStream_t s);
+qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, int eo, float4* out_e, const float4* in_e,
+                              hipStream_t s);
 qxd_status qxd_schur_apply_mixed(qxd_handle* h, int dagger, float4* out_e, const float4* in_e, double* norm_slot,
                                  hipStream_t s);

@@ -10,25 +10,36 @@
 // workgroup per block and no races: x is read outside the block (other colour)
 // and written inside it.  ncy cycles (colour 0 then 1) from x = 0 give M eta.
 //
+// Block solver.  The paper's SAP solves the blocks by minimal-residual steps
+// on the block's even-odd Schur complement D_hat_B = H_ee - D_eo H_oo^-1 D_oe,
+// from the source r_e - D_eo H_oo^-1 r_o, and back-substitutes
+// e_o = H_oo^-1 (r_o - D_oe e_e) (eo = 1); eo = 0 runs the steps on D_B itself.
+//
 // Block layout.  The even-odd half fields keep x3 fastest, so the 256 sites of
 // a block sit in runs of two consecutive half indices, and a workgroup reading
 // them would use a fraction of every cache line it pulls.  SAP therefore works
-// on copies in block order: component k of site t (local index
-// 64 l0 + 16 l1 + 4 l2 + l3) of block B at (B * ncomp + k) * 256 + t, blocks
-// numbered colour-major (B = colour * nhalf + j, j the workgroup of that colour's
-// launch).  The links (36 float2 a site, forward links of both parities) and the
-// clover blocks (18 float4) are copied once per gauge field and flavour; the
-// iterate x and the source eta (6 float4) live in block order for the whole
-// application, and only the first and last half cycles touch the half fields.
+// on copies in block order: component k of the site in slot t of block B at
+// (B * ncomp + k) * 256 + t, blocks numbered colour-major (B = colour * nhalf +
+// j, j the workgroup of that colour's launch).  The plain solver keeps the
+// local index s = 64 l0 + 16 l1 + 4 l2 + l3 as the slot; the even-odd one sorts
+// a block's sites by parity, the site of parity q in slot 128 q + s / 2, so
+// that each wavefront holds sites of one parity.  The
+// links (36 float2 a site, forward links of both parities), the clover blocks
+// (18 float4) and, on odd sites, their inverses are copied once per gauge field
+// and flavour; the iterate x and the source eta (6 float4) live in block order
+// for the whole application, and only the first and last half cycles touch the
+// half fields.
 //
 // A workgroup of 256 threads owns one block, one thread per site; a site keeps
-// its four forward links in registers.  Each application of D_B every site
-// publishes its spinor (24.6 kB of LDS) and, for each direction, the backward
-// hop it owes its forward neighbour, (1 + g_mu) U^+ rho as two colour vectors
-// (49.2 kB): 74 kB of LDS per block, so two blocks share a CU.  The residual at
-// entry uses the same exchange for the in-block part of D x and global loads
-// for the hops that cross the block's faces.  The block reductions of the
-// minimal-residual step go through LDS.
+// its four forward links in registers.  A hop exchange publishes the spinor of
+// the sending sites (24.6 kB of LDS for all 256) and, for each direction, the
+// backward hop each owes its forward neighbour, (1 + g_mu) U^+ rho as two
+// colour vectors (49.2 kB): 74 kB of LDS per block, so two blocks share a CU.
+// With eo = 1 the even wavefronts send while the odd ones receive and the other
+// way round; senders and receivers touch disjoint slots, so one barrier per
+// exchange suffices.  The residual at entry uses the same exchange for the
+// in-block part of D x and global loads for the hops that cross the block's
+// faces.  The block reductions of the minimal-residual step go through LDS.
 #include "blas.hpp"
 #include "wilson_site.hpp"
 
@@ -42,12 +53,37 @@ struct SapGeo {
   int nhalf;          // blocks of one colour
 };
 
-// Block-order index B * 256 + t of the site x.
+// Slot of the site with local index s and its inverse: parity-sorted for the
+// even-odd block solver (EO), the local index itself for the plain one.
+template <bool EO>
+__device__ __forceinline__ int sap_slot(int s) {
+  if (!EO) return s;
+  const int q = ((s >> 6) ^ (s >> 4) ^ (s >> 2) ^ s) & 1;
+  return (q << 7) | (s >> 1);
+}
+template <bool EO>
+__device__ __forceinline__ void sap_local(int t, int& l0, int& l1, int& l2, int& l3) {
+  if (!EO) {
+    l0 = t >> 6;
+    l1 = (t >> 4) & 3;
+    l2 = (t >> 2) & 3;
+    l3 = t & 3;
+    return;
+  }
+  const int q = t >> 7, k = t & 127;
+  l0 = k >> 5;
+  l1 = (k >> 3) & 3;
+  l2 = (k >> 1) & 3;
+  l3 = 2 * (k & 1) + ((l0 + l1 + l2 + q) & 1);
+}
+
+// Block-order index B * 256 + slot of the site x.
+template <bool EO>
 __device__ __forceinline__ int sap_bsite(const SapGeo& sb, int x0, int x1, int x2, int x3) {
   const int c0 = x0 >> 2, c1 = x1 >> 2, c2 = x2 >> 2, c3 = x3 >> 2;
   const int j = ((c0 * sb.nb1 + c1) * sb.nb2 + c2) * (sb.nb3 >> 1) + (c3 >> 1);
   const int B = ((c0 + c1 + c2 + c3) & 1) * sb.nhalf + j;
-  return B * kSapSites + (((x0 & 3) << 6) | ((x1 & 3) << 4) | ((x2 & 3) << 2) | (x3 & 3));
+  return B * kSapSites + sap_slot<EO>(((x0 & 3) << 6) | ((x1 & 3) << 4) | ((x2 & 3) << 2) | (x3 & 3));
 }
 
 // Coordinates of block j of the given colour: along x3 the colours alternate.
@@ -68,17 +104,21 @@ __device__ __forceinline__ T* sap_blk(T* base, int B) {
   return base + (size_t)B * NC * kSapSites;
 }
 
-// Block-order copies of the links and the clover blocks (one thread per site).
+// Block-order copies of the links, the clover blocks and, for EO, the inverses
+// on odd sites (one thread per site; CIb holds 128 odd slots a block).
+template <bool EO>
 __global__ __launch_bounds__(kSapSites) void k_sap_pack(Geo g, SapGeo sb, const float2* __restrict__ V32,
                                                         const float4* __restrict__ He,
-                                                        const float4* __restrict__ Ho, float2* __restrict__ Vb,
-                                                        float4* __restrict__ Cb) {
+                                                        const float4* __restrict__ Ho,
+                                                        const float4* __restrict__ Hi, float2* __restrict__ Vb,
+                                                        float4* __restrict__ Cb, float4* __restrict__ CIb) {
   const int B = blockIdx.x, colour = B >= sb.nhalf ? 1 : 0;
   int c0, c1, c2, c3;
   sap_block_coords(sb, colour, B - colour * sb.nhalf, c0, c1, c2, c3);
   const int t = threadIdx.x;
-  const int x0 = kSapB * c0 + (t >> 6), x1 = kSapB * c1 + ((t >> 4) & 3), x2 = kSapB * c2 + ((t >> 2) & 3),
-            x3 = kSapB * c3 + (t & 3);
+  int l0, l1, l2, l3;
+  sap_local<EO>(t, l0, l1, l2, l3);
+  const int x0 = kSapB * c0 + l0, x1 = kSapB * c1 + l1, x2 = kSapB * c2 + l2, x3 = kSapB * c3 + l3;
   const int p = (x0 + x1 + x2 + x3) & 1;
   const size_t Ve = g.Ve, h = geo_half(g, x0, x1, x2, x3);
   const float2* Vp = V32 + (size_t)p * 36 * Ve;
@@ -89,22 +129,31 @@ __global__ __launch_bounds__(kSapSites) void k_sap_pack(Geo g, SapGeo sb, const 
   for (int k = 0; k < 36; ++k) vb[k * kSapSites + t] = Vp[k * Ve + h];
 #pragma unroll 6
   for (int k = 0; k < 18; ++k) cb[k * kSapSites + t] = Hp[k * Ve + h];
+  if (EO && p) {
+    float4* ci = CIb + (size_t)B * 18 * (kSapSites / 2) + (t - kSapSites / 2);
+#pragma unroll 6
+    for (int k = 0; k < 18; ++k) ci[k * (kSapSites / 2)] = Hi[k * Ve + h];
+  }
 }
 
-// Plain (cached) loads: every step of a block solve reads the clover blocks again.
-__device__ __forceinline__ void sap_clover(const float4* __restrict__ cb, int t, const cx<float> in[12],
+// Plain (cached) loads: every step of a block solve reads the clover blocks
+// again.  cb points at the site's first component, components STRIDE apart.
+template <int STRIDE>
+__device__ __forceinline__ void sap_clover(const float4* __restrict__ cb, const cx<float> in[12],
                                            cx<float> out[12]) {
-  float r[72];
 #pragma unroll
-  for (int k = 0; k < 18; ++k) {
-    float4 v = cb[k * kSapSites + t];
-    r[4 * k] = v.x;
-    r[4 * k + 1] = v.y;
-    r[4 * k + 2] = v.z;
-    r[4 * k + 3] = v.w;
+  for (int half = 0; half < 2; ++half) {  // one 6 x 6 block at a time: 36 registers of clover
+    float r[36];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float4 v = cb[(9 * half + k) * STRIDE];
+      r[4 * k] = v.x;
+      r[4 * k + 1] = v.y;
+      r[4 * k + 2] = v.z;
+      r[4 * k + 3] = v.w;
+    }
+    herm6_mul<float>(r, in + 6 * half, out + 6 * half);
   }
-  herm6_mul<float>(r, in, out);
-  herm6_mul<float>(r + 36, in + 6, out + 6);
 }
 
 // The backward hop that site t contributes to its forward neighbour along MU:
@@ -122,28 +171,32 @@ __device__ __forceinline__ void sap_send(float2 (*bw_s)[6][kSapSites], int t, co
   }
 }
 
-// Both in-block hops along MU at site t (local coordinate l along MU, strides
-// 64, 16, 4, 1): forward with the site's own link and the neighbour's rho,
-// backward as sent by the neighbour.
-template <int MU>
-__device__ __forceinline__ void sap_recv(const float4 (*rho_s)[kSapSites], const float2 (*bw_s)[6][kSapSites], int t,
-                                         int l, const cx<float> u[9], cx<float> acc[12]) {
+// Both in-block hops along MU at the site with local index s and parity q
+// (local coordinate l along MU; local-index strides 64, 16, 4, 1): forward with
+// the site's own link and the neighbour's rho, backward as sent by the
+// neighbour.  Neighbours have the other parity: with EO, slot 128 (1 - q) + s' / 2.
+template <int MU, bool EO>
+__device__ __forceinline__ void sap_recv(const float4 (*rho_s)[kSapSites], const float2 (*bw_s)[6][kSapSites], int s,
+                                         int q, int l, const cx<float> u[9], cx<float> acc[12]) {
   constexpr int st = MU == 0 ? 64 : MU == 1 ? 16 : MU == 2 ? 4 : 1;
+  const int other = EO ? (q ^ 1) << 7 : 0;
   if (l < kSapB - 1) {
-    cx<float> s[12];
+    const int tn = EO ? other | ((s + st) >> 1) : s + st;
+    cx<float> f[12];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      float4 v = rho_s[j][t + st];
-      s[2 * j] = mk(v.x, v.y);
-      s[2 * j + 1] = mk(v.z, v.w);
+      float4 v = rho_s[j][tn];
+      f[2 * j] = mk(v.x, v.y);
+      f[2 * j + 1] = mk(v.z, v.w);
     }
-    hop_term<MU, true>(acc, s, u, false);
+    hop_term<MU, true>(acc, f, u, false);
   }
   if (l > 0) {
+    const int tn = EO ? other | ((s - st) >> 1) : s - st;
     cx<float> w0[3], w1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      float2 v0 = bw_s[MU][a][t - st], v1 = bw_s[MU][3 + a][t - st];
+      float2 v0 = bw_s[MU][a][tn], v1 = bw_s[MU][3 + a][tn];
       w0[a] = mk(v0.x, v0.y);
       w1[a] = mk(v1.x, v1.y);
     }
@@ -154,7 +207,7 @@ __device__ __forceinline__ void sap_recv(const float4 (*rho_s)[kSapSites], const
 // The hop along MU that leaves the block at site x (local coordinate l along
 // MU): forward from the face l = 3 with the site's own link u, backward from
 // the face l = 0 with the neighbour's link; the neighbour's x in block order.
-template <int MU>
+template <int MU, bool EO>
 __device__ __forceinline__ void sap_face(const Geo& g, const SapGeo& sb, int x0, int x1, int x2, int x3, int l,
                                          const float4* __restrict__ Xb, const float2* __restrict__ Vb,
                                          const cx<float> u[9], cx<float> acc[12]) {
@@ -162,12 +215,12 @@ __device__ __forceinline__ void sap_face(const Geo& g, const SapGeo& sb, int x0,
   cx<float> s[12];
   if (l == kSapB - 1) {
     geo_step<MU, +1>(g, x0, x1, x2, x3, neg);
-    const int bs = sap_bsite(sb, x0, x1, x2, x3);
+    const int bs = sap_bsite<EO>(sb, x0, x1, x2, x3);
     sp_load(sap_blk<6>(Xb, bs >> 8), kSapSites, bs & 255, s);
     hop_term<MU, true>(acc, s, u, neg);
   } else if (l == 0) {
     geo_step<MU, -1>(g, x0, x1, x2, x3, neg);
-    const int bs = sap_bsite(sb, x0, x1, x2, x3);
+    const int bs = sap_bsite<EO>(sb, x0, x1, x2, x3);
     sp_load(sap_blk<6>(Xb, bs >> 8), kSapSites, bs & 255, s);
     cx<float> v[9];
     const float2* vb = sap_blk<36>(Vb, bs >> 8) + MU * 9 * kSapSites + (bs & 255);
@@ -192,24 +245,76 @@ struct SapLds {
   float red[3][kSapSites / 64];
 };
 
-// acc = the in-block hops of f at site t: f and the backward hops are exchanged
-// through LDS (every earlier read of the exchange buffers has passed a barrier
-// before the call).
-__device__ __forceinline__ void sap_inblock(SapLds& L, int t, int l0, int l1, int l2, int l3, const cx<float> f[12],
-                                            const cx<float> (*U)[9], cx<float> acc[12]) {
+// Where a thread sits in its block: slot t, local index s, parity q, local
+// coordinates l (cheap to recompute from the thread index wherever needed).
+struct SapSite {
+  int t, s, q, l0, l1, l2, l3;
+};
+template <bool EO>
+__device__ __forceinline__ SapSite sap_site() {
+  SapSite w;
+  w.t = threadIdx.x;
+  sap_local<EO>(w.t, w.l0, w.l1, w.l2, w.l3);
+  w.q = (w.l0 + w.l1 + w.l2 + w.l3) & 1;
+  w.s = (w.l0 << 6) | (w.l1 << 4) | (w.l2 << 2) | w.l3;
+  return w;
+}
+
+// Publish f at the site (slot t) and the backward hops it owes its forward
+// neighbours.
+template <bool EO>
+__device__ __forceinline__ void sap_publish(SapLds& L, const cx<float> f[12], const cx<float> (*U)[9]) {
+  const SapSite w = sap_site<EO>();
 #pragma unroll
-  for (int j = 0; j < 6; ++j) L.rho[j][t] = make_float4(f[2 * j].re, f[2 * j].im, f[2 * j + 1].re, f[2 * j + 1].im);
-  if (l0 < kSapB - 1) sap_send<0>(L.bw, t, f, U[0]);
-  if (l1 < kSapB - 1) sap_send<1>(L.bw, t, f, U[1]);
-  if (l2 < kSapB - 1) sap_send<2>(L.bw, t, f, U[2]);
-  if (l3 < kSapB - 1) sap_send<3>(L.bw, t, f, U[3]);
-  __syncthreads();
+  for (int j = 0; j < 6; ++j)
+    L.rho[j][w.t] = make_float4(f[2 * j].re, f[2 * j].im, f[2 * j + 1].re, f[2 * j + 1].im);
+  if (w.l0 < kSapB - 1) sap_send<0>(L.bw, w.t, f, U[0]);
+  if (w.l1 < kSapB - 1) sap_send<1>(L.bw, w.t, f, U[1]);
+  if (w.l2 < kSapB - 1) sap_send<2>(L.bw, w.t, f, U[2]);
+  if (w.l3 < kSapB - 1) sap_send<3>(L.bw, w.t, f, U[3]);
+}
+
+// acc = the in-block hops at the site of what its neighbours published.
+template <bool EO>
+__device__ __forceinline__ void sap_gather(const SapLds& L, const cx<float> (*U)[9], cx<float> acc[12]) {
+  const SapSite w = sap_site<EO>();
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = mk(0.f, 0.f);
-  sap_recv<0>(L.rho, L.bw, t, l0, U[0], acc);
-  sap_recv<1>(L.rho, L.bw, t, l1, U[1], acc);
-  sap_recv<2>(L.rho, L.bw, t, l2, U[2], acc);
-  sap_recv<3>(L.rho, L.bw, t, l3, U[3], acc);
+  sap_recv<0, EO>(L.rho, L.bw, w.s, w.q, w.l0, U[0], acc);
+  sap_recv<1, EO>(L.rho, L.bw, w.s, w.q, w.l1, U[1], acc);
+  sap_recv<2, EO>(L.rho, L.bw, w.s, w.q, w.l2, U[2], acc);
+  sap_recv<3, EO>(L.rho, L.bw, w.s, w.q, w.l3, U[3], acc);
+}
+
+// Block sums of (v, rho) and (v, v) over the workgroup (one barrier).
+__device__ __forceinline__ cx<float> sap_alpha(SapLds& L, int t, const cx<float> v[12], const cx<float> rho[12]) {
+  float are = 0.f, aim = 0.f, nn = 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    cx<float> vr = cmul_conj(v[c], rho[c]);  // conj(v) rho
+    are += vr.re;
+    aim += vr.im;
+    nn += norm2(v[c]);
+  }
+  are = sap_wave_sum(are);
+  aim = sap_wave_sum(aim);
+  nn = sap_wave_sum(nn);
+  const int wave = t >> 6;
+  if ((t & 63) == 0) {
+    L.red[0][wave] = are;
+    L.red[1][wave] = aim;
+    L.red[2][wave] = nn;
+  }
+  __syncthreads();
+  are = aim = nn = 0.f;
+#pragma unroll
+  for (int k = 0; k < kSapSites / 64; ++k) {
+    are += L.red[0][k];
+    aim += L.red[1][k];
+    nn += L.red[2][k];
+  }
+  // alpha = (v, rho) / (v, v); a block whose residual vanished stays put
+  return nn > 0.f ? mk(are / nn, aim / nn) : mk(0.f, 0.f);
 }
 
 enum { SAP_FIRST = 0, SAP_MID = 1, SAP_LAST = 2 };
@@ -222,26 +327,28 @@ enum { SAP_FIRST = 0, SAP_MID = 1, SAP_LAST = 2 };
 //   SAP_MID:   r = eta - D x from the block-order fields;
 //   SAP_LAST:  as SAP_MID, then writes the even sites of the block's x and of
 //              its partner's (final after this half cycle) to out_e.
-template <int MODE>
+// EO: even-odd preconditioned block solves (waves 0, 1 hold the even sites).
+template <int MODE, bool EO>
 __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int colour, int nmr,
                                                            const float4* __restrict__ eta_e,
                                                            float4* __restrict__ Eb, float4* __restrict__ Xb,
                                                            const float2* __restrict__ Vb,
                                                            const float4* __restrict__ Cb,
+                                                           const float4* __restrict__ CIb,
                                                            float4* __restrict__ out_e) {
   __shared__ SapLds L;
   const int j = blockIdx.x;
   int c0, c1, c2, c3;
   sap_block_coords(sb, colour, j, c0, c1, c2, c3);
   const int B = colour * sb.nhalf + j, Bp = (1 - colour) * sb.nhalf + j;
-  const int t = threadIdx.x;
-  const int l0 = t >> 6, l1 = (t >> 4) & 3, l2 = (t >> 2) & 3, l3 = t & 3;
-  const int x0 = kSapB * c0 + l0, x1 = kSapB * c1 + l1, x2 = kSapB * c2 + l2, x3 = kSapB * c3 + l3;
-  const int p = (x0 + x1 + x2 + x3) & 1;
-  // the partner's site with the same local index (same parity: x3 moves by 4)
+  const SapSite w = sap_site<EO>();
+  const int t = w.t, q = w.q;  // q: the site's parity (block origins are even)
+  const int x0 = kSapB * c0 + w.l0, x1 = kSapB * c1 + w.l1, x2 = kSapB * c2 + w.l2, x3 = kSapB * c3 + w.l3;
+  // the partner's site in the same slot (same parity: x3 moves by 4)
   const int x3p = x3 + ((c3 & 1) ? -kSapB : kSapB);
   const size_t Ve = g.Ve;
-  const float4* cb = sap_blk<18>(Cb, B);
+  const float4* cb = sap_blk<18>(Cb, B) + t;
+  const float4* ci = CIb + (size_t)B * 18 * (kSapSites / 2) + (t - kSapSites / 2);  // odd slots only
   float4* xb = sap_blk<6>(Xb, B);
   float4* eb = sap_blk<6>(Eb, B);
 
@@ -259,7 +366,7 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
   }
   cx<float> rho[12];
   if (MODE == SAP_FIRST) {
-    if (p == 0) {
+    if (q == 0) {
       sp_load(eta_e, Ve, geo_half(g, x0, x1, x2, x3), rho);
       sp_store(eb, kSapSites, t, rho);
       cx<float> ep[12];
@@ -277,14 +384,16 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
     // r = eta - D x = eta - H x + (1/2) (in-block hops + hops across the faces)
     cx<float> xs[12], acc[12];
     sp_load(xb, kSapSites, t, xs);
-    sap_inblock(L, t, l0, l1, l2, l3, xs, U, acc);
-    sap_face<0>(g, sb, x0, x1, x2, x3, l0, Xb, Vb, U[0], acc);
-    sap_face<1>(g, sb, x0, x1, x2, x3, l1, Xb, Vb, U[1], acc);
-    sap_face<2>(g, sb, x0, x1, x2, x3, l2, Xb, Vb, U[2], acc);
-    sap_face<3>(g, sb, x0, x1, x2, x3, l3, Xb, Vb, U[3], acc);
+    sap_publish<EO>(L, xs, U);
+    __syncthreads();
+    sap_gather<EO>(L, U, acc);
+    sap_face<0, EO>(g, sb, x0, x1, x2, x3, w.l0, Xb, Vb, U[0], acc);
+    sap_face<1, EO>(g, sb, x0, x1, x2, x3, w.l1, Xb, Vb, U[1], acc);
+    sap_face<2, EO>(g, sb, x0, x1, x2, x3, w.l2, Xb, Vb, U[2], acc);
+    sap_face<3, EO>(g, sb, x0, x1, x2, x3, w.l3, Xb, Vb, U[3], acc);
     cx<float> hx[12];
-    sap_clover(cb, t, xs, hx);
-    if (p == 0) {
+    sap_clover<kSapSites>(cb, xs, hx);
+    if (q == 0) {
       sp_load(eb, kSapSites, t, rho);
     } else {
 #pragma unroll
@@ -295,47 +404,91 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
     __syncthreads();  // the exchange buffers are published again below
   }
 
+  // e: the block solution; with EO the odd sites keep r_o in it until the
+  // back substitution
   cx<float> e[12];
+  if (!EO) {
 #pragma unroll
-  for (int c = 0; c < 12; ++c) e[c] = mk(0.f, 0.f);
-  const int wave = t >> 6, lane = t & 63;
-  for (int step = 0; step < nmr; ++step) {
-    // v = D_B rho = H rho - (1/2) (in-block hops); every read of the previous
-    // step's exchange buffers came before its reduction barrier
-    cx<float> acc[12], v[12];
-    sap_inblock(L, t, l0, l1, l2, l3, rho, U, acc);
-    sap_clover(cb, t, rho, v);
-    float are = 0.f, aim = 0.f, nn = 0.f;
+    for (int c = 0; c < 12; ++c) e[c] = mk(0.f, 0.f);
+    for (int step = 0; step < nmr; ++step) {
+      // v = D_B rho = H rho - (1/2) (in-block hops); every read of the previous
+      // step's exchange buffers came before its reduction barrier
+      cx<float> acc[12], v[12];
+      sap_publish<EO>(L, rho, U);
+      __syncthreads();
+      sap_gather<EO>(L, U, acc);
+      sap_clover<kSapSites>(cb, rho, v);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      v[c] = v[c] - 0.5f * acc[c];
-      cx<float> vr = cmul_conj(v[c], rho[c]);  // conj(v) rho
-      are += vr.re;
-      aim += vr.im;
-      nn += norm2(v[c]);
+      for (int c = 0; c < 12; ++c) v[c] = v[c] - 0.5f * acc[c];
+      const cx<float> alpha = sap_alpha(L, t, v, rho);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        e[c] = e[c] + alpha * rho[c];
+        rho[c] = rho[c] - alpha * v[c];
+      }
     }
-    are = sap_wave_sum(are);
-    aim = sap_wave_sum(aim);
-    nn = sap_wave_sum(nn);
-    if (lane == 0) {
-      L.red[0][wave] = are;
-      L.red[1][wave] = aim;
-      L.red[2][wave] = nn;
+  } else {
+    // Sends and receives of one exchange touch the slots of opposite parities,
+    // so a wave may publish right after it gathered.
+#pragma unroll
+    for (int c = 0; c < 12; ++c) e[c] = q ? rho[c] : mk(0.f, 0.f);
+    if (MODE != SAP_FIRST) {
+      // source of the Schur system: r_e - D_eo H_oo^-1 r_o = r_e + (1/2) hops(H_oo^-1 r_o)
+      if (q == 1) {
+        cx<float> so[12];
+        sap_clover<kSapSites / 2>(ci, rho, so);
+        sap_publish<EO>(L, so, U);
+      }
+      __syncthreads();
+      if (q == 0) {
+        cx<float> acc[12];
+        sap_gather<EO>(L, U, acc);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) rho[c] = rho[c] + 0.5f * acc[c];
+      }
     }
+    for (int step = 0; step < nmr; ++step) {
+      // v = D_hat_B rho = H_ee rho + (1/2) hops(t_o), t_o = -(1/2) H_oo^-1 hops(rho)
+      if (q == 0) sap_publish<EO>(L, rho, U);
+      __syncthreads();
+      if (q == 1) {
+        cx<float> acc[12], to[12];
+        sap_gather<EO>(L, U, acc);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = -0.5f * acc[c];
+        sap_clover<kSapSites / 2>(ci, acc, to);
+        sap_publish<EO>(L, to, U);
+      }
+      __syncthreads();
+      cx<float> v[12];
+      if (q == 0) {
+        cx<float> acc[12];
+        sap_gather<EO>(L, U, acc);
+        sap_clover<kSapSites>(cb, rho, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = v[c] + 0.5f * acc[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = mk(0.f, 0.f);
+      }
+      const cx<float> alpha = sap_alpha(L, t, v, rho);
+      if (q == 0) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          e[c] = e[c] + alpha * rho[c];
+          rho[c] = rho[c] - alpha * v[c];
+        }
+      }
+    }
+    // back substitution: e_o = H_oo^-1 (r_o - D_oe e_e) = H_oo^-1 (r_o + (1/2) hops(e_e))
+    if (q == 0) sap_publish<EO>(L, e, U);
     __syncthreads();
-    are = aim = nn = 0.f;
+    if (q == 1) {
+      cx<float> acc[12];
+      sap_gather<EO>(L, U, acc);
 #pragma unroll
-    for (int w = 0; w < kSapSites / 64; ++w) {
-      are += L.red[0][w];
-      aim += L.red[1][w];
-      nn += L.red[2][w];
-    }
-    // alpha = (v, rho) / (v, v); a block whose residual vanished stays put
-    const cx<float> alpha = nn > 0.f ? mk(are / nn, aim / nn) : mk(0.f, 0.f);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      e[c] = e[c] + alpha * rho[c];
-      rho[c] = rho[c] - alpha * v[c];
+      for (int c = 0; c < 12; ++c) acc[c] = e[c] + 0.5f * acc[c];
+      sap_clover<kSapSites / 2>(ci, acc, e);
     }
   }
   if (MODE != SAP_FIRST) {
@@ -345,7 +498,7 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
     for (int c = 0; c < 12; ++c) e[c] = e[c] + xs[c];
   }
   sp_store(xb, kSapSites, t, e);
-  if (MODE == SAP_LAST && p == 0) {
+  if (MODE == SAP_LAST && q == 0) {
     sp_store(out_e, Ve, geo_half(g, x0, x1, x2, x3), e);
     cx<float> xp[12];
     sp_load(sap_blk<6>(Xb, Bp), kSapSites, t, xp);
@@ -354,8 +507,30 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
 }
 
 // workspace roles (free in the solvers' table): block-order links, clover
-// blocks, iterate and source
-enum { W_SAP_VB = 8, W_SAP_CB = 9, W_SAP_XB = 13, W_SAP_EB = 14 };
+// blocks, iterate, source and odd-site clover inverses
+enum { W_SAP_VB = 8, W_SAP_CB = 9, W_SAP_XB = 13, W_SAP_EB = 14, W_SAP_CIB = 15 };
+
+struct SapArgs {
+  Geo g;
+  SapGeo sb;
+  int nmr;
+  const float4* eta_e;
+  float4 *Eb, *Xb;
+  const float2* Vb;
+  const float4 *Cb, *CIb;
+  float4* out_e;
+};
+
+template <int MODE>
+void sap_launch(bool eo, const SapArgs& a, int colour, hipStream_t s) {
+  const dim3 grid(a.sb.nhalf), blk(kSapSites);
+  if (eo)
+    hipLaunchKernelGGL((k_sap_half<MODE, true>), grid, blk, 0, s, a.g, a.sb, colour, a.nmr, a.eta_e, a.Eb, a.Xb, a.Vb,
+                       a.Cb, a.CIb, a.out_e);
+  else
+    hipLaunchKernelGGL((k_sap_half<MODE, false>), grid, blk, 0, s, a.g, a.sb, colour, a.nmr, a.eta_e, a.Eb, a.Xb,
+                       a.Vb, a.Cb, a.CIb, a.out_e);
+}
 
 }  // namespace
 
@@ -369,40 +544,48 @@ bool sap_supported(const qxd_handle* h) {
   return g.cstar < 2 || (g.L1 / kSapB) % 2 == 0;
 }
 
-qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, float4* out_e, const float4* in_e, hipStream_t s) {
-  if (ncy < 1 || nmr < 1 || ncy > 64 || nmr > 64) return QXD_EINVAL;
+qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, int eo, float4* out_e, const float4* in_e,
+                              hipStream_t s) {
+  if (ncy < 1 || nmr < 1 || ncy > 64 || nmr > 64 || (eo != 0 && eo != 1)) return QXD_EINVAL;
   if (!h->has_inverse) return QXD_ESTATE;
   if (!sap_supported(h)) return QXD_EGEOM;
   const size_t V = (size_t)h->V;
   float2* Vb = (float2*)ws_get(h, W_SAP_VB, V * 36 * sizeof(float2));
   float4* Cb = (float4*)ws_get(h, W_SAP_CB, V * 18 * sizeof(float4));
+  float4* CIb = (float4*)ws_get(h, W_SAP_CIB, V / 2 * 18 * sizeof(float4));
   float4* Xb = (float4*)ws_get(h, W_SAP_XB, V * 6 * sizeof(float4));
   float4* Eb = (float4*)ws_get(h, W_SAP_EB, V * 6 * sizeof(float4));
-  if (!Vb || !Cb || !Xb || !Eb) return QXD_ENOMEM;
+  if (!Vb || !Cb || !CIb || !Xb || !Eb) return QXD_ENOMEM;
   const Geo& g = h->geo;
   const int nblk = (g.Le0 / kSapB) * (g.Le1 / kSapB) * (g.Le2 / kSapB) * (g.Le3 / kSapB);
   const SapGeo sb{g.Le1 / kSapB, g.Le2 / kSapB, g.Le3 / kSapB, nblk / 2};
-  if (h->sap_gen != h->setup_gen) {  // links or clover changed since the last copy
-    hipLaunchKernelGGL(k_sap_pack, dim3(nblk), dim3(kSapSites), 0, s, g, sb, reinterpret_cast<const float2*>(h->V32),
-                       reinterpret_cast<const float4*>(h->He32), reinterpret_cast<const float4*>(h->Ho32), Vb, Cb);
+  // the copies are tagged 2 setup_gen + eo: repacked when the links, the clover
+  // blocks or the slot order changed since the last copy
+  const uint64_t tag = 2 * h->setup_gen + (uint64_t)eo;
+  if (h->sap_gen != tag) {
+    auto pack = eo ? k_sap_pack<true> : k_sap_pack<false>;
+    hipLaunchKernelGGL(pack, dim3(nblk), dim3(kSapSites), 0, s, g, sb, reinterpret_cast<const float2*>(h->V32),
+                       reinterpret_cast<const float4*>(h->He32), reinterpret_cast<const float4*>(h->Ho32),
+                       reinterpret_cast<const float4*>(h->Hi32), Vb, Cb, CIb);
     QXD_HIP(hipGetLastError());
-    h->sap_gen = h->setup_gen;
+    h->sap_gen = tag;
   }
-  const dim3 grid(sb.nhalf), blk(kSapSites);
+  const SapArgs a{g, sb, nmr, in_e, Eb, Xb, Vb, Cb, CIb, out_e};
   for (int cy = 0; cy < ncy; ++cy)
     for (int colour = 0; colour < 2; ++colour) {
       if (cy == 0 && colour == 0)
-        hipLaunchKernelGGL(k_sap_half<SAP_FIRST>, grid, blk, 0, s, g, sb, colour, nmr, in_e, Eb, Xb, Vb, Cb, out_e);
+        sap_launch<SAP_FIRST>(eo, a, colour, s);
       else if (cy == ncy - 1 && colour == 1)
-        hipLaunchKernelGGL(k_sap_half<SAP_LAST>, grid, blk, 0, s, g, sb, colour, nmr, in_e, Eb, Xb, Vb, Cb, out_e);
+        sap_launch<SAP_LAST>(eo, a, colour, s);
       else
-        hipLaunchKernelGGL(k_sap_half<SAP_MID>, grid, blk, 0, s, g, sb, colour, nmr, in_e, Eb, Xb, Vb, Cb, out_e);
+        sap_launch<SAP_MID>(eo, a, colour, s);
     }
   QXD_HIP(hipGetLastError());
   return QXD_OK;
 }
 
-extern "C" qxd_status qxd_sap_apply(qxd_handle* h, int ncy, int nmr, void* out_e, const void* in_e, void* stream) {
+extern "C" qxd_status qxd_sap_apply(qxd_handle* h, int ncy, int nmr, int eo, void* out_e, const void* in_e,
+                                    void* stream) {
   if (!h || !out_e || !in_e || out_e == in_e) return QXD_EINVAL;
-  return sap_apply_internal(h, ncy, nmr, (float4*)out_e, (const float4*)in_e, as_stream(stream));
+  return sap_apply_internal(h, ncy, nmr, eo, (float4*)out_e, (const float4*)in_e, as_stream(stream));
 }

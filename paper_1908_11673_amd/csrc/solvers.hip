@@ -107,7 +107,7 @@ qxd_status cgnr(qxd_handle* h, InnerOp op, VT* x, VT* r, VT* p, VT* z, VT* w, si
 // The right preconditioner of the inner FGCR: the network or SAP (FP32 only).
 struct Precond {
   qxd_nn* net = nullptr;
-  int sap_ncy = 0, sap_nmr = 0;
+  int sap_ncy = 0, sap_nmr = 0, sap_eo = 1;
   bool any() const { return net != nullptr || sap_ncy > 0; }
 };
 
@@ -116,7 +116,7 @@ qxd_status precond_apply(qxd_handle* h, const Precond& pc, VT* out, const VT* in
 template <>
 qxd_status precond_apply<float4>(qxd_handle* h, const Precond& pc, float4* out, const float4* in, hipStream_t s) {
   if (pc.net) return nn_apply_internal(h, pc.net, out, in, s);
-  return sap_apply_internal(h, pc.sap_ncy, pc.sap_nmr, out, in, s);
+  return sap_apply_internal(h, pc.sap_ncy, pc.sap_nmr, pc.sap_eo, out, in, s);
 }
 template <>
 qxd_status precond_apply<double2>(qxd_handle*, const Precond&, double2*, const double2*, hipStream_t) {
@@ -398,9 +398,11 @@ extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm
   pc.net = net;
   if (prm->sap_ncy > 0) {
     if (net || prm->sap_nmr < 1) return QXD_EINVAL;  // one preconditioner at a time
+    if (prm->sap_plain != 0 && prm->sap_plain != 1) return QXD_EINVAL;
     if (!sap_supported(h)) return QXD_EGEOM;
     pc.sap_ncy = prm->sap_ncy;
     pc.sap_nmr = prm->sap_nmr;
+    pc.sap_eo = 1 - prm->sap_plain;
   }
   if (mode == 0 && pc.any()) return QXD_EINVAL;  // the preconditioners run on FP32 vectors
   hipStream_t s = as_stream(stream);

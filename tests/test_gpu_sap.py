@@ -1,6 +1,7 @@
 """SAP preconditioner on the GPU through the C ABI: parity with the FP64 oracle
-(same seeded fields and sources; the GPU runs in FP32: the bar is the FP32
-operator tolerance 1e-6 in norm, measured 1e-7 after five cycles),
+for both block solvers, even-odd preconditioned and plain (same seeded fields
+and sources; the GPU runs in FP32: the bar is the FP32 operator tolerance 1e-6
+in norm, measured 1e-7 after five cycles),
 geometry checks, and SAP-preconditioned FGCR solves to the FP64 true residual
 1e-10 checked by the oracle's D."""
 import numpy as np
@@ -24,22 +25,24 @@ FD = sg.FLAVOURS["d"]
 def pair(request):
     L, cstar = request.param
     o, lat, _ = make_pair(L, cstar, FD, sigma=0.2, su1=0.3, seed=41)
-    yield o, lat
+    blocks = osap.site_blocks(o)
+    yield o, lat, blocks
     lat.close()
 
 
+@pytest.mark.parametrize("eo", [1, 0], ids=["eo", "plain"])
 @pytest.mark.parametrize("ncy,nmr", [(1, 1), (2, 3), (5, 5)])
-def test_sap_matches_the_oracle(pair, ncy, nmr):
-    o, lat = pair
+def test_sap_matches_the_oracle(pair, ncy, nmr, eo):
+    o, lat, blocks = pair
     assert osap.supported(o)
     r = sg.spinor(61, o.V)
     r[o.parity() == 1] = 0
     out = lat.field(qxd.F32)
-    qxd.qxd_sap_apply(lat.h, ncy, nmr, out, half32(lat, r))
+    qxd.qxd_sap_apply(lat.h, ncy, nmr, eo, out, half32(lat, r))
     got = from_half32(lat, out)
-    want = osap.sap_even(o, r, ncy, nmr)
+    want = osap.sap_even(o, r, ncy, nmr, bool(eo), blocks)
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
-    print("sap ncy %d nmr %d: rel err %.2e" % (ncy, nmr, err))
+    print("sap eo %d ncy %d nmr %d: rel err %.2e" % (eo, ncy, nmr, err))
     assert err < 1e-6
     assert np.abs(got[o.parity() == 1]).max() == 0
 
@@ -50,22 +53,32 @@ def test_sap_rejects_lattices_the_colouring_does_not_fit():
     A = sg.gauge_u1(1, 0.3, 8 * 4 * 8 * 8)
     lat.setup(U, A, FD)
     out, inp = lat.field(qxd.F32), lat.field(qxd.F32)
-    assert qxd.load().qxd_sap_apply(lat.h, 1, 1, qxd._ptr(out), qxd._ptr(inp), None) == 2
-    assert qxd.load().qxd_sap_apply(lat.h, 0, 1, qxd._ptr(out), qxd._ptr(inp), None) in (1, 2)
+    assert qxd.load().qxd_sap_apply(lat.h, 1, 1, 1, qxd._ptr(out), qxd._ptr(inp), None) == 2
+    assert qxd.load().qxd_sap_apply(lat.h, 0, 1, 1, qxd._ptr(out), qxd._ptr(inp), None) in (1, 2)
     lat.close()
 
 
+def test_sap_rejects_bad_arguments(pair):
+    o, lat, _ = pair
+    out, inp = lat.field(qxd.F32), lat.field(qxd.F32)
+    for ncy, nmr, eo in ((0, 1, 1), (1, 0, 1), (65, 1, 1), (1, 65, 0), (1, 1, 2), (1, 1, -1)):
+        assert qxd.load().qxd_sap_apply(lat.h, ncy, nmr, eo, qxd._ptr(out), qxd._ptr(inp), None) == 1
+    assert qxd.load().qxd_sap_apply(lat.h, 1, 1, 1, qxd._ptr(out), qxd._ptr(out), None) == 1
+
+
+@pytest.mark.parametrize("sap_plain", [0, 1], ids=["eo", "plain"])
 @pytest.mark.parametrize("inner", [qxd.F32, qxd.BF16], ids=["f32", "bf16links"])
-def test_sap_fgcr_solves_to_1e10(pair, inner):
-    o, lat = pair
+def test_sap_fgcr_solves_to_1e10(pair, inner, sap_plain):
+    o, lat, _ = pair
     b = sg.spinor(62, o.V)
     bd = lat.pack(to_dev(b))
     x = lat.field(qxd.F64, full=True)
     plain = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner), None, x, bd)
     x = lat.field(qxd.F64, full=True)
-    st = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner, sap_ncy=4, sap_nmr=4), None, x, bd)
-    print("plain %d steps, SAP %d steps (%d SAP applications)" % (plain["inner_it"], st["inner_it"],
-                                                                   st["sap_applies"]))
+    prm = qxd.solver_params(res=1e-10, inner_prec=inner, sap_ncy=4, sap_nmr=4, sap_plain=sap_plain)
+    st = qxd.qxd_solve_fgcr(lat.h, prm, None, x, bd)
+    print("no preconditioner %d steps, SAP %d steps (%d SAP applications)" % (
+        plain["inner_it"], st["inner_it"], st["sap_applies"]))
     assert st["status"] == 0 and st["true_residual"] <= 1e-10 and st["fell_back"] == 0
     assert st["sap_applies"] >= st["inner_it"] and st["inner_it"] < plain["inner_it"]
     res = np.linalg.norm(b - o.dirac(lat.unpack(x).cpu().numpy())) / np.linalg.norm(b)
