@@ -229,6 +229,46 @@ qxd_status qxd_solve_fgcr(qxd_handle *h, const qxd_solver_params *params, qxd_nn
 qxd_status qxd_sap_apply(qxd_handle *h, int ncy, int nmr, int eo, void *out_e, const void *in_e, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Shifted normal solves and the RHMC rational operator (App. A of the paper;
+ * the MSCG solver of its sample input, App. C).  M = D_hat^+ D_hat on the even
+ * sites; FP64 throughout.  Of the solver parameters these read nmx (iteration
+ * limit), res (relative residual asked of every shifted system) and
+ * check_every (iterations between the host's convergence checks).
+ */
+#define QXD_MS_MAXSHIFT 24
+
+/* Multi-shift CG: x_e[j] = (M + shifts[j])^-1 b_e for j < nshift, all from one
+ * Krylov space (CG on the smallest shift, the others by the shifted-CG scalar
+ * recurrences; a shift stops once its residual is below res |b_e|).  With the
+ * shifts mu^2 these are the twisted-mass normal solves (D_hat^+ D_hat + mu^2).
+ * shifts: host array of nshift values >= 0; x_e: host array of nshift device
+ * pointers to distinct FP64 even half fields (caller-owned, overwritten);
+ * b_e: FP64 even half field, not one of x_e.  stats->inner_it: iterations;
+ * stats->true_residual: the largest |b - (M + s_j) x_j| / |b| recomputed at the
+ * end; stats->schur_applies: D_hat and D_hat^+ applications.  The library holds
+ * nshift + 3 FP64 half fields of workspace.  QXD_EINVAL for nshift outside
+ * 1..QXD_MS_MAXSHIFT, a negative or non-finite shift, aliased or NULL fields;
+ * QXD_ESTATE before the clover inverse; QXD_ENOCONV when nmx iterations do not
+ * reach res; QXD_ENAN on a non-finite residual. */
+qxd_status qxd_solve_mscg(qxd_handle *h, const qxd_solver_params *prm, int nshift, const double *shifts,
+                          void *const *x_e, const void *b_e, qxd_solver_stats *stats, void *stream);
+
+/* The rational operator out_e = A prod_{j<n} (M + nu_j^2) (M + mu_j^2)^-1 in_e
+ * (App. A.1), evaluated by partial fractions, A (1 + sum_j sigma_j
+ * (M + mu_j^2)^-1) with sigma_j = (nu_j^2 - mu_j^2) prod_{m != j} (nu_m^2 -
+ * mu_j^2) / (mu_m^2 - mu_j^2) (App. A.2), and one multi-shift solve whose
+ * solutions are summed as they converge (never stored).  A factor P_{k,l} of a
+ * frequency-split approximation is the call with A = 1 and the sub-arrays
+ * nu + k, mu + k, n = l - k + 1.  nu, mu: host arrays, the mu_j^2 distinct;
+ * in_e, out_e: FP64 even half fields (may alias).  stats->true_residual: the
+ * largest recurrence residual |zeta_j r| / |in| of the shifted systems at their
+ * last update (not recomputed).  Errors as qxd_solve_mscg, and QXD_EINVAL for
+ * repeated mu_j^2. */
+qxd_status qxd_rational_apply(qxd_handle *h, const qxd_solver_params *prm, double A, int n, const double *nu,
+                              const double *mu, void *out_e, const void *in_e, qxd_solver_stats *stats,
+                              void *stream);
+
+/* ---------------------------------------------------------------------------
  * Learned preconditioner: three 3^4-tap convolutions on the extended lattice
  * whose taps follow the C* neighbour map (x + d is a composition of unit steps),
  * real channels 24 -> 32 -> 32 -> 24, no biases, ReLU after layers 1 and 2.

@@ -76,6 +76,7 @@ def _struct_dict(s):
     return {name: getattr(s, name) for name, _ in s._fields_}
 
 
+QXD_MS_MAXSHIFT = 24  # most shifts of one multi-shift solve (include/qxd.h)
 _P, _I, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
 _SIGNATURES = {
     "qxd_status_string": ([_I], ctypes.c_char_p),
@@ -96,6 +97,10 @@ _SIGNATURES = {
     "qxd_solve_cg": ([_P, ctypes.POINTER(qxd_solver_params), _P, _P, ctypes.POINTER(qxd_solver_stats), _P], _I),
     "qxd_solve_fgcr": ([_P, ctypes.POINTER(qxd_solver_params), _P, _P, _P, ctypes.POINTER(qxd_solver_stats), _P],
                        _I),
+    "qxd_solve_mscg": ([_P, ctypes.POINTER(qxd_solver_params), _I, ctypes.POINTER(_D), ctypes.POINTER(_P), _P,
+                        ctypes.POINTER(qxd_solver_stats), _P], _I),
+    "qxd_rational_apply": ([_P, ctypes.POINTER(qxd_solver_params), _D, _I, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                            _P, _P, ctypes.POINTER(qxd_solver_stats), _P], _I),
     "qxd_nn_create": ([_P, ctypes.POINTER(_P)], _I),
     "qxd_nn_destroy": ([_P], _I),
     "qxd_nn_set_weights": ([_P, _P], _I),
@@ -257,6 +262,35 @@ def qxd_solve_fgcr(h, params, net, x, b, stream=None, check=True):
                                  _stream(stream))
     if check:
         _check(code, "qxd_solve_fgcr")
+    d = _struct_dict(st)
+    d["status"] = code
+    return d
+
+
+def qxd_solve_mscg(h, params, shifts, xs, b_e, stream=None, check=True):
+    """x_e[j] = (D_hat^+ D_hat + shifts[j])^-1 b_e for every shift (FP64 even half fields)."""
+    n = len(shifts)
+    st = qxd_solver_stats()
+    sh = (_D * n)(*[float(v) for v in shifts])
+    ptrs = (_P * n)(*[_ptr(x) for x in xs])
+    code = load().qxd_solve_mscg(h, ctypes.byref(params), n, sh, ptrs, _ptr(b_e), ctypes.byref(st), _stream(stream))
+    if check:
+        _check(code, "qxd_solve_mscg")
+    d = _struct_dict(st)
+    d["status"] = code
+    return d
+
+
+def qxd_rational_apply(h, params, A, nu, mu, out_e, in_e, stream=None, check=True):
+    """out_e = A prod_j (D_hat^+ D_hat + nu_j^2) / (D_hat^+ D_hat + mu_j^2) in_e (FP64 even half fields)."""
+    n = len(nu)
+    st = qxd_solver_stats()
+    nu_c = (_D * n)(*[float(v) for v in nu])
+    mu_c = (_D * n)(*[float(v) for v in mu])
+    code = load().qxd_rational_apply(h, ctypes.byref(params), float(A), n, nu_c, mu_c, _ptr(out_e), _ptr(in_e),
+                                     ctypes.byref(st), _stream(stream))
+    if check:
+        _check(code, "qxd_rational_apply")
     d = _struct_dict(st)
     d["status"] = code
     return d

@@ -51,3 +51,17 @@ def from_half32(lat, t):
     full = lat.field(qxd.F32, full=True)
     full[:12 * lat.Ve] = t
     return lat.unpack(full, qxd.F32).cpu().numpy()
+
+
+def half64(lat, psi):
+    """even-site spinor (V, 4, 3) -> FP64 even half field on the device"""
+    import paper_1908_11673_amd as qxd
+    return lat.pack(to_dev(psi), qxd.F64)[:12 * lat.Ve].clone()
+
+
+def from_half64(lat, t):
+    """FP64 even half field -> (V, 4, 3) complex128 spinor (odd sites zero)"""
+    import paper_1908_11673_amd as qxd
+    full = lat.field(qxd.F64, full=True)
+    full[:12 * lat.Ve] = t
+    return lat.unpack(full, qxd.F64).cpu().numpy()
