@@ -15,8 +15,10 @@ once per pass: 288; clover blocks H_e and H_o^-1: 144; spinors: 120).
 
 Extra legs (not part of `value`): the time to a true FP64 residual 1e-10 of FP64
 CG against mixed-precision FGCR (and, when a trained network is available,
-network-preconditioned FGCR) on the same lattice; and the FP64 CPU oracle timed
-on a bounded sample of even sites of the same lattice (`cpu_baseline`).
+network-preconditioned FGCR) on the same lattice; FP64 shifted normal solves
+(the paper's rational operator by multi-shift CG, twisted-mass systems solved
+together and one by one); and the FP64 CPU oracle timed on a bounded sample of
+even sites of the same lattice (`cpu_baseline`).
 """
 from __future__ import annotations
 
@@ -213,6 +215,8 @@ def main():
         train = not big and (not only or "fgcr_f32_nn_in_f64" in only)
         result["time_to_solution"] = solve_leg(qxd, torch, lats, w, flavours, args.nn_fields if train else 0,
                                                args.nn_epochs, big, only)
+        if not big and (not only or "shifted" in only):
+            result["shifted_solves"] = shifted_leg(qxd, torch, lats, w, flavours)
 
     if not args.no_cpu_baseline and not big:  # the oracle would hold 60 GB of host fields at 128 x 64^3
         log("cpu baseline (oracle) ...")
@@ -275,6 +279,66 @@ def copy_calibration(torch):
 # here (half the wavefronts wait in each of its two hop exchanges): 153 ms
 # against 128 ms at its best setting.
 SAP_NCY, SAP_NMR, SAP_PLAIN = 2, 8, 1
+
+
+def read_rational(path=os.path.join(ROOT, "tests", "golden", "rational0.txt")):
+    """The [Rational 0] approximation printed in the paper's sample input file."""
+    t = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        key, *vals = line.split()
+        t[key] = [float(v) for v in vals]
+    return t["A"][0], t["nu"], t["mus"], t["delta"][0]
+
+
+TM_MU = (0.003, 0.01, 0.03, 0.1)  # twisted masses of the shifted-solve leg
+
+
+def shifted_leg(qxd, torch, lats, w, flavours):
+    """FP64 shifted normal solves on the benchmark lattice, one Gaussian source
+    per flavour: the rational operator R of the paper's [Rational 0]
+    approximation (ten poles, one multi-shift solve to 1e-11), and the
+    twisted-mass systems (D_hat^+ D_hat + mu^2) for the masses TM_MU solved
+    together by multi-shift CG against one after another."""
+    import synthgen as sg
+    A, nu, mu, delta = read_rational()
+    out = {}
+    b = sg.spinor(w["source_seed"] + 2, lats[0].V)
+    for lat, name in zip(lats, ("qhat-2", "qhat+4")):
+        res = {}
+        phi = lat.pack(torch.from_numpy(b).cuda())[:12 * lat.Ve].clone()
+        torch.cuda.empty_cache()
+        y = lat.field(qxd.F64)
+
+        def timed(fn):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3, st
+
+        ms, st = timed(lambda: qxd.qxd_rational_apply(lat.h, qxd.solver_params(res=1e-11, check_every=8), A, nu, mu,
+                                                      y, phi, check=False))
+        res["rational_r0"] = {"ms": round(ms, 2), "status": st["status"], "iterations": st["inner_it"],
+                              "poles": len(mu), "schur_applies": st["schur_applies"],
+                              "recurrence_residual": st["true_residual"], "delta": delta}
+        log("%s rational operator (%d poles): %.1f ms, %d iterations" % (name, len(mu), ms, st["inner_it"]))
+        prm = qxd.solver_params(res=1e-10, check_every=8)
+        xs = [lat.field(qxd.F64) for _ in TM_MU]
+        ms_all, st = timed(lambda: qxd.qxd_solve_mscg(lat.h, prm, [m * m for m in TM_MU], xs, phi, check=False))
+        res["tm_multishift"] = {"ms": round(ms_all, 2), "status": st["status"], "iterations": st["inner_it"],
+                                "true_residual": st["true_residual"], "mu": list(TM_MU)}
+        ms_sep, its = 0.0, 0
+        for m, x in zip(TM_MU, xs):
+            ms1, st = timed(lambda: qxd.qxd_solve_mscg(lat.h, prm, [m * m], [x], phi, check=False))
+            ms_sep += ms1
+            its += st["inner_it"]
+        res["tm_one_by_one"] = {"ms": round(ms_sep, 2), "iterations": its}
+        log("%s twisted-mass solves, mu %s: together %.1f ms, one by one %.1f ms" % (name, TM_MU, ms_all, ms_sep))
+        del xs, y
+        out[name] = res
+    return out
 
 
 def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, only=()):
