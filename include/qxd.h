@@ -105,6 +105,7 @@ typedef struct {
   int sap_ncy;         /* FGCR: > 0 selects the SAP preconditioner with this many cycles (net must be NULL) */
   int sap_nmr;         /* SAP: minimal-residual steps per block solve */
   int sap_plain;       /* SAP: 0 (default) even-odd preconditioned block solves, 1 plain (see qxd_sap_apply) */
+  int dfl_nc;          /* deflation: coarse GCR steps per preconditioner application (1..QXD_DFL_MAXNC; 0: 16) */
 } qxd_solver_params;
 
 typedef struct {
@@ -121,6 +122,7 @@ typedef struct {
 
 typedef struct qxd_handle qxd_handle;
 typedef struct qxd_nn qxd_nn;
+typedef struct qxd_dfl qxd_dfl;
 
 /* Status name for printing. */
 const char *qxd_status_string(qxd_status s);
@@ -207,6 +209,12 @@ qxd_status qxd_solve_cg(qxd_handle *h, const qxd_solver_params *params, void *x,
  * non-finite or the residual stalls for fallback_after steps. */
 qxd_status qxd_solve_fgcr(qxd_handle *h, const qxd_solver_params *params, qxd_nn *net, void *x, const void *b,
                           qxd_solver_stats *stats, void *stream);
+/* FGCR as qxd_solve_fgcr, preconditioned by deflation with SAP (qxd_dfl_apply):
+ * params->sap_ncy (>= 1), sap_nmr, sap_plain for the SAP part and
+ * params->dfl_nc coarse steps; FP32 or bf16-link inner solves.
+ * stats->sap_applies counts the preconditioner applications. */
+qxd_status qxd_solve_fgcr_dfl(qxd_handle *h, const qxd_solver_params *params, qxd_dfl *dfl, void *x,
+                              const void *b, qxd_solver_stats *stats, void *stream);
 
 /* SAP, the paper's Schwarz alternating procedure preconditioner (Sec. 4.4,
  * SAP+GCR), applied to the Schur system: out_e = (M (in_e, 0))_e, where M is
@@ -227,6 +235,53 @@ qxd_status qxd_solve_fgcr(qxd_handle *h, const qxd_solver_params *params, qxd_nn
  * ncy or nmr outside 1..64 or eo not 0 or 1; QXD_ESTATE before the clover
  * inverse.  Also the FGCR preconditioner (qxd_solver_params.sap_ncy). */
 qxd_status qxd_sap_apply(qxd_handle *h, int ncy, int nmr, int eo, void *out_e, const void *in_e, void *stream);
+/* The same SAP on full FP32 fields (even half, then odd half, 12 Ve complex64):
+ * out = M in with in nonzero on both parities; in, out distinct. */
+qxd_status qxd_sap_apply_full(qxd_handle *h, int ncy, int nmr, int eo, void *out, const void *in, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Inexact deflation (the paper's DFL+SAP+GCR, Sec. 4.4), FP32.  A deflation
+ * subspace of ns vectors is made rich in low modes by approximate inverse
+ * iteration (v <- M_sap v / |M_sap v|, plain SAP block solves), cut into the 4^4
+ * SAP blocks and orthonormalised block by block (basis W); the little operator
+ * A = W^+ D W couples a block to itself and its 8 face neighbours.  The
+ * preconditioner is psi + M_sap (eta - D psi), psi = W c with c from nc GCR
+ * steps on A c = W^+ eta (an inexact coarse solve).  A subspace belongs to the
+ * operator it was made with: one per quark charge (qxd_dfl_little rebuilds A for
+ * another operator from the same basis).  The geometry must admit SAP
+ * (QXD_EGEOM otherwise).
+ */
+#define QXD_DFL_MAXNS 24
+#define QXD_DFL_MAXNC 32
+
+/* A deflation object for the handle's lattice: basis, little operator and work
+ * fields (96 ns + 192 bytes per extended site and 72 ns^2 bytes per block);
+ * ns in 1..QXD_DFL_MAXNS.  Destroy it before the handle. */
+qxd_status qxd_dfl_create(qxd_handle *h, int ns, qxd_dfl **d);
+qxd_status qxd_dfl_destroy(qxd_dfl *d);
+/* Build the subspace from ns start vectors v (FP32 full fields, contiguous,
+ * 12 Ve complex64 each, device; overwritten with the vectors after nit rounds
+ * of inverse iteration with ncy SAP cycles of nmr steps), then the basis and the
+ * little operator for the handle's current operator.  QXD_ESTATE before the
+ * clover inverse; QXD_EINVAL for nit outside 0..100 or bad SAP parameters. */
+qxd_status qxd_dfl_generate(qxd_handle *h, qxd_dfl *d, void *v, int nit, int ncy, int nmr, void *stream);
+/* Rebuild the little operator for the handle's current operator (after a new
+ * flavour or gauge field) from the same basis. */
+qxd_status qxd_dfl_little(qxd_handle *h, qxd_dfl *d, void *stream);
+/* The preconditioner of the Schur system: out_e = (M (in_e, 0))_e with nc
+ * coarse GCR steps (1..QXD_DFL_MAXNC) and ncy SAP cycles of nmr steps (eo as in
+ * qxd_sap_apply); FP32 even half fields, distinct.  QXD_ESTATE when the little
+ * operator was built for another operator than the handle's. */
+qxd_status qxd_dfl_apply(qxd_handle *h, qxd_dfl *d, int nc, int ncy, int nmr, int eo, void *out_e,
+                         const void *in_e, void *stream);
+/* Basis vector k of every block as one FP32 full field (device). */
+qxd_status qxd_dfl_basis(qxd_handle *h, qxd_dfl *d, int k, void *out, void *stream);
+/* Copy the little operator (nblk * 9 * ns * ns complex64, [block][n][l][k]) and
+ * the neighbour table (nblk * 9 ints; n = 0 the block, 1 + 2 mu its +mu and
+ * 2 + 2 mu its -mu neighbour) to host memory.  Blocks are numbered colour-major
+ * (all blocks of even block-coordinate parity first, x3 fastest). */
+qxd_status qxd_dfl_little_get(qxd_dfl *d, float *A, int *nbr);
+qxd_status qxd_dfl_size(const qxd_dfl *d, int *nblk, int *ns);
 
 /* ---------------------------------------------------------------------------
  * Shifted normal solves and the RHMC rational operator (App. A of the paper;

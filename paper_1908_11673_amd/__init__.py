@@ -51,7 +51,7 @@ class qxd_solver_params(ctypes.Structure):
     _fields_ = [("nmx", ctypes.c_int), ("res", ctypes.c_double), ("inner_prec", ctypes.c_int),
                 ("inner_res", ctypes.c_double), ("nkv", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("fallback_after", ctypes.c_int), ("sap_ncy", ctypes.c_int),
-                ("sap_nmr", ctypes.c_int), ("sap_plain", ctypes.c_int)]
+                ("sap_nmr", ctypes.c_int), ("sap_plain", ctypes.c_int), ("dfl_nc", ctypes.c_int)]
 
 
 class qxd_solver_stats(ctypes.Structure):
@@ -101,6 +101,16 @@ _SIGNATURES = {
                         ctypes.POINTER(qxd_solver_stats), _P], _I),
     "qxd_rational_apply": ([_P, ctypes.POINTER(qxd_solver_params), _D, _I, ctypes.POINTER(_D), ctypes.POINTER(_D),
                             _P, _P, ctypes.POINTER(qxd_solver_stats), _P], _I),
+    "qxd_solve_fgcr_dfl": ([_P, ctypes.POINTER(qxd_solver_params), _P, _P, _P, ctypes.POINTER(qxd_solver_stats),
+                            _P], _I),
+    "qxd_dfl_create": ([_P, _I, ctypes.POINTER(_P)], _I),
+    "qxd_dfl_destroy": ([_P], _I),
+    "qxd_dfl_generate": ([_P, _P, _P, _I, _I, _I, _P], _I),
+    "qxd_dfl_little": ([_P, _P, _P], _I),
+    "qxd_dfl_apply": ([_P, _P, _I, _I, _I, _I, _P, _P, _P], _I),
+    "qxd_dfl_basis": ([_P, _P, _I, _P, _P], _I),
+    "qxd_dfl_little_get": ([_P, _P, _P], _I),
+    "qxd_dfl_size": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
     "qxd_nn_create": ([_P, ctypes.POINTER(_P)], _I),
     "qxd_nn_destroy": ([_P], _I),
     "qxd_nn_set_weights": ([_P, _P], _I),
@@ -108,6 +118,7 @@ _SIGNATURES = {
     "qxd_nn_get_weights": ([_P, _P], _I),
     "qxd_nn_apply": ([_P, _P, _P, _P, _P], _I),
     "qxd_sap_apply": ([_P, _I, _I, _I, _P, _P, _P], _I),
+    "qxd_sap_apply_full": ([_P, _I, _I, _I, _P, _P, _P], _I),
     "qxd_nn_loss_grad": ([_P, _P, _P, _P, _I, _I, ctypes.POINTER(_D), _P, _P], _I),
     "qxd_nn_harvest": ([_P, _P, _I, _P, _P, ctypes.POINTER(_I), _P], _I),
     "qxd_nn_train": ([_P, _P, ctypes.POINTER(qxd_train_params), _P, _P, _I, ctypes.POINTER(qxd_train_stats), _P],
@@ -241,9 +252,10 @@ def qxd_unpack(h, prec, aos, soa, stream=None):
 
 
 def solver_params(nmx=100000, res=1e-10, inner_prec=F32, inner_res=1e-5, nkv=16, max_outer=100, check_every=4,
-                  fallback_after=50, sap_ncy=0, sap_nmr=4, sap_plain=0):
+                  fallback_after=50, sap_ncy=0, sap_nmr=4, sap_plain=0, dfl_nc=0):
     return qxd_solver_params(int(nmx), float(res), int(inner_prec), float(inner_res), int(nkv), int(max_outer),
-                             int(check_every), int(fallback_after), int(sap_ncy), int(sap_nmr), int(sap_plain))
+                             int(check_every), int(fallback_after), int(sap_ncy), int(sap_nmr), int(sap_plain),
+                             int(dfl_nc))
 
 
 def qxd_solve_cg(h, params, x, b, stream=None, check=True):
@@ -296,6 +308,62 @@ def qxd_rational_apply(h, params, A, nu, mu, out_e, in_e, stream=None, check=Tru
     return d
 
 
+QXD_DFL_MAXNS, QXD_DFL_MAXNC = 24, 32  # include/qxd.h
+
+
+def qxd_solve_fgcr_dfl(h, params, dfl, x, b, stream=None, check=True):
+    st = qxd_solver_stats()
+    code = load().qxd_solve_fgcr_dfl(h, ctypes.byref(params), dfl, _ptr(x), _ptr(b), ctypes.byref(st),
+                                     _stream(stream))
+    if check:
+        _check(code, "qxd_solve_fgcr_dfl")
+    d = _struct_dict(st)
+    d["status"] = code
+    return d
+
+
+def qxd_dfl_create(h, ns):
+    d = _P()
+    _check(load().qxd_dfl_create(h, int(ns), ctypes.byref(d)), "qxd_dfl_create")
+    return d.value
+
+
+def qxd_dfl_destroy(d):
+    _check(load().qxd_dfl_destroy(d), "qxd_dfl_destroy")
+
+
+def qxd_dfl_generate(h, d, v, nit, ncy, nmr, stream=None):
+    _check(load().qxd_dfl_generate(h, d, _ptr(v), int(nit), int(ncy), int(nmr), _stream(stream)), "qxd_dfl_generate")
+
+
+def qxd_dfl_little(h, d, stream=None):
+    _check(load().qxd_dfl_little(h, d, _stream(stream)), "qxd_dfl_little")
+
+
+def qxd_dfl_apply(h, d, nc, ncy, nmr, eo, out_e, in_e, stream=None):
+    _check(load().qxd_dfl_apply(h, d, int(nc), int(ncy), int(nmr), int(eo), _ptr(out_e), _ptr(in_e), _stream(stream)),
+           "qxd_dfl_apply")
+
+
+def qxd_dfl_basis(h, d, k, out, stream=None):
+    _check(load().qxd_dfl_basis(h, d, int(k), _ptr(out), _stream(stream)), "qxd_dfl_basis")
+
+
+def qxd_dfl_size(d):
+    nb, ns = _I(), _I()
+    _check(load().qxd_dfl_size(d, ctypes.byref(nb), ctypes.byref(ns)), "qxd_dfl_size")
+    return nb.value, ns.value
+
+
+def qxd_dfl_little_get(d):
+    """(A as complex64 [nblk][9][ns][ns], nbr [nblk][9]) on the host."""
+    nblk, ns = qxd_dfl_size(d)
+    A = np.zeros((nblk, 9, ns, ns), dtype=np.complex64)
+    nbr = np.zeros((nblk, 9), dtype=np.int32)
+    _check(load().qxd_dfl_little_get(d, A.ctypes.data, nbr.ctypes.data), "qxd_dfl_little_get")
+    return A, nbr
+
+
 def qxd_nn_create(h):
     net = _P()
     _check(load().qxd_nn_create(h, ctypes.byref(net)), "qxd_nn_create")
@@ -325,6 +393,11 @@ def qxd_nn_get_weights(net):
 def qxd_sap_apply(h, ncy, nmr, eo, out_e, in_e, stream=None):
     _check(load().qxd_sap_apply(h, int(ncy), int(nmr), int(eo), _ptr(out_e), _ptr(in_e), _stream(stream)),
            "qxd_sap_apply")
+
+
+def qxd_sap_apply_full(h, ncy, nmr, eo, out, inp, stream=None):
+    _check(load().qxd_sap_apply_full(h, int(ncy), int(nmr), int(eo), _ptr(out), _ptr(inp), _stream(stream)),
+           "qxd_sap_apply_full")
 
 
 def qxd_nn_apply(h, net, out_e, in_e, stream=None):

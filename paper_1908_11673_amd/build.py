@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libqxd.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "gauge.hip", "clover.hip", "dirac.hip", "blas.hip", "solvers.hip", "nn.hip", "sap.hip", "mscg.hip"]
+SOURCES = ["api.hip", "gauge.hip", "clover.hip", "dirac.hip", "blas.hip", "solvers.hip", "nn.hip", "sap.hip", "mscg.hip", "dfl.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-munsafe-fp-atomics",

@@ -361,6 +361,7 @@ inline void* ws_get(qxd_handle* h, int i, size_t bytes) {
 }
 
 struct qxd_nn;
+struct qxd_dfl;
 
 // error helpers
 #define QXD_HIP(call)                            \
@@ -385,9 +386,13 @@ void launch_final_sum(const double* partial, int n, int nvals, int stride, doubl
 qxd_status qxd_schur_apply(qxd_handle* h, qxd_prec p, int dagger, void* out_e, const void* in_e, double* norm_slot,
                            hipStream_t s);
 qxd_status nn_apply_internal(qxd_handle* h, qxd_nn* net, float4* out_e, const float4* in_e, hipStream_t s);
-// SAP preconditioner of the Schur system (sap.hip): out_e = (M_SAP (in_e, 0))_e
+// DFL+SAP preconditioner of the Schur system (dfl.hip): out_e = (M_DFL (in_e, 0))_e
+qxd_status dfl_apply_internal(qxd_handle* h, qxd_dfl* d, int nc, int ncy, int nmr, int eo, float4* out_e,
+                              const float4* in_e, hipStream_t s);
+// SAP (sap.hip) on FP32 fields: out_e = (M_SAP (in_e, in_o))_e, in_o = 0 when
+// null, and the odd half of M_SAP (in_e, in_o) into out_o when given
 bool sap_supported(const qxd_handle* h);
 qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, int eo, float4* out_e, const float4* in_e,
-                              hipStream_t s);
+                              hipStream_t s, const float4* in_o = nullptr, float4* out_o = nullptr);
 qxd_status qxd_schur_apply_mixed(qxd_handle* h, int dagger, float4* out_e, const float4* in_e, double* norm_slot,
                                  hipStream_t s);

@@ -41,68 +41,9 @@
 // in-block part of D x and global loads for the hops that cross the block's
 // faces.  The block reductions of the minimal-residual step go through LDS.
 #include "blas.hpp"
-#include "wilson_site.hpp"
+#include "sap_blocks.hpp"
 
 namespace {
-
-constexpr int kSapB = 4;                            // block extent
-constexpr int kSapSites = kSapB * kSapB * kSapB * kSapB;  // 256: one thread per site
-
-struct SapGeo {
-  int nb1, nb2, nb3;  // blocks along x1, x2, x3 (nb3 even)
-  int nhalf;          // blocks of one colour
-};
-
-// Slot of the site with local index s and its inverse: parity-sorted for the
-// even-odd block solver (EO), the local index itself for the plain one.
-template <bool EO>
-__device__ __forceinline__ int sap_slot(int s) {
-  if (!EO) return s;
-  const int q = ((s >> 6) ^ (s >> 4) ^ (s >> 2) ^ s) & 1;
-  return (q << 7) | (s >> 1);
-}
-template <bool EO>
-__device__ __forceinline__ void sap_local(int t, int& l0, int& l1, int& l2, int& l3) {
-  if (!EO) {
-    l0 = t >> 6;
-    l1 = (t >> 4) & 3;
-    l2 = (t >> 2) & 3;
-    l3 = t & 3;
-    return;
-  }
-  const int q = t >> 7, k = t & 127;
-  l0 = k >> 5;
-  l1 = (k >> 3) & 3;
-  l2 = (k >> 1) & 3;
-  l3 = 2 * (k & 1) + ((l0 + l1 + l2 + q) & 1);
-}
-
-// Block-order index B * 256 + slot of the site x.
-template <bool EO>
-__device__ __forceinline__ int sap_bsite(const SapGeo& sb, int x0, int x1, int x2, int x3) {
-  const int c0 = x0 >> 2, c1 = x1 >> 2, c2 = x2 >> 2, c3 = x3 >> 2;
-  const int j = ((c0 * sb.nb1 + c1) * sb.nb2 + c2) * (sb.nb3 >> 1) + (c3 >> 1);
-  const int B = ((c0 + c1 + c2 + c3) & 1) * sb.nhalf + j;
-  return B * kSapSites + sap_slot<EO>(((x0 & 3) << 6) | ((x1 & 3) << 4) | ((x2 & 3) << 2) | (x3 & 3));
-}
-
-// Coordinates of block j of the given colour: along x3 the colours alternate.
-__device__ __forceinline__ void sap_block_coords(const SapGeo& sb, int colour, int j, int& c0, int& c1, int& c2,
-                                                 int& c3) {
-  const int half3 = sb.nb3 >> 1;
-  const int k3 = j % half3;
-  int line = j / half3;
-  c2 = line % sb.nb2;
-  line /= sb.nb2;
-  c1 = line % sb.nb1;
-  c0 = line / sb.nb1;
-  c3 = 2 * k3 + ((c0 + c1 + c2 + colour) & 1);
-}
-
-template <int NC, class T>
-__device__ __forceinline__ T* sap_blk(T* base, int B) {
-  return base + (size_t)B * NC * kSapSites;
-}
 
 // Block-order copies of the links, the clover blocks and, for EO, the inverses
 // on odd sites (one thread per site; CIb holds 128 odd slots a block).
@@ -136,74 +77,6 @@ __global__ __launch_bounds__(kSapSites) void k_sap_pack(Geo g, SapGeo sb, const 
   }
 }
 
-// Plain (cached) loads: every step of a block solve reads the clover blocks
-// again.  cb points at the site's first component, components STRIDE apart.
-template <int STRIDE>
-__device__ __forceinline__ void sap_clover(const float4* __restrict__ cb, const cx<float> in[12],
-                                           cx<float> out[12]) {
-#pragma unroll
-  for (int half = 0; half < 2; ++half) {  // one 6 x 6 block at a time: 36 registers of clover
-    float r[36];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      float4 v = cb[(9 * half + k) * STRIDE];
-      r[4 * k] = v.x;
-      r[4 * k + 1] = v.y;
-      r[4 * k + 2] = v.z;
-      r[4 * k + 3] = v.w;
-    }
-    herm6_mul<float>(r, in + 6 * half, out + 6 * half);
-  }
-}
-
-// The backward hop that site t contributes to its forward neighbour along MU:
-// (1 + g_MU) U(t, MU)^+ rho(t), kept as the two multiplied colour vectors.
-template <int MU>
-__device__ __forceinline__ void sap_send(float2 (*bw_s)[6][kSapSites], int t, const cx<float> rho[12],
-                                         const cx<float> u[9]) {
-  cx<float> h0[3], h1[3], w0[3], w1[3];
-  spin_project<MU, false>(rho, h0, h1);
-  colour_mul<false>(u, h0, h1, w0, w1);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    bw_s[MU][a][t] = make_float2(w0[a].re, w0[a].im);
-    bw_s[MU][3 + a][t] = make_float2(w1[a].re, w1[a].im);
-  }
-}
-
-// Both in-block hops along MU at the site with local index s and parity q
-// (local coordinate l along MU; local-index strides 64, 16, 4, 1): forward with
-// the site's own link and the neighbour's rho, backward as sent by the
-// neighbour.  Neighbours have the other parity: with EO, slot 128 (1 - q) + s' / 2.
-template <int MU, bool EO>
-__device__ __forceinline__ void sap_recv(const float4 (*rho_s)[kSapSites], const float2 (*bw_s)[6][kSapSites], int s,
-                                         int q, int l, const cx<float> u[9], cx<float> acc[12]) {
-  constexpr int st = MU == 0 ? 64 : MU == 1 ? 16 : MU == 2 ? 4 : 1;
-  const int other = EO ? (q ^ 1) << 7 : 0;
-  if (l < kSapB - 1) {
-    const int tn = EO ? other | ((s + st) >> 1) : s + st;
-    cx<float> f[12];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      float4 v = rho_s[j][tn];
-      f[2 * j] = mk(v.x, v.y);
-      f[2 * j + 1] = mk(v.z, v.w);
-    }
-    hop_term<MU, true>(acc, f, u, false);
-  }
-  if (l > 0) {
-    const int tn = EO ? other | ((s - st) >> 1) : s - st;
-    cx<float> w0[3], w1[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      float2 v0 = bw_s[MU][a][tn], v1 = bw_s[MU][3 + a][tn];
-      w0[a] = mk(v0.x, v0.y);
-      w1[a] = mk(v1.x, v1.y);
-    }
-    spin_rebuild_add<MU, false>(acc, w0, w1);
-  }
-}
-
 // The hop along MU that leaves the block at site x (local coordinate l along
 // MU): forward from the face l = 3 with the site's own link u, backward from
 // the face l = 0 with the neighbour's link; the neighbour's x in block order.
@@ -231,59 +104,6 @@ __device__ __forceinline__ void sap_face(const Geo& g, const SapGeo& sb, int x0,
     }
     hop_term<MU, false>(acc, s, v, neg);
   }
-}
-
-__device__ __forceinline__ float sap_wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-struct SapLds {
-  float4 rho[6][kSapSites];
-  float2 bw[4][6][kSapSites];
-  float red[3][kSapSites / 64];
-};
-
-// Where a thread sits in its block: slot t, local index s, parity q, local
-// coordinates l (cheap to recompute from the thread index wherever needed).
-struct SapSite {
-  int t, s, q, l0, l1, l2, l3;
-};
-template <bool EO>
-__device__ __forceinline__ SapSite sap_site() {
-  SapSite w;
-  w.t = threadIdx.x;
-  sap_local<EO>(w.t, w.l0, w.l1, w.l2, w.l3);
-  w.q = (w.l0 + w.l1 + w.l2 + w.l3) & 1;
-  w.s = (w.l0 << 6) | (w.l1 << 4) | (w.l2 << 2) | w.l3;
-  return w;
-}
-
-// Publish f at the site (slot t) and the backward hops it owes its forward
-// neighbours.
-template <bool EO>
-__device__ __forceinline__ void sap_publish(SapLds& L, const cx<float> f[12], const cx<float> (*U)[9]) {
-  const SapSite w = sap_site<EO>();
-#pragma unroll
-  for (int j = 0; j < 6; ++j)
-    L.rho[j][w.t] = make_float4(f[2 * j].re, f[2 * j].im, f[2 * j + 1].re, f[2 * j + 1].im);
-  if (w.l0 < kSapB - 1) sap_send<0>(L.bw, w.t, f, U[0]);
-  if (w.l1 < kSapB - 1) sap_send<1>(L.bw, w.t, f, U[1]);
-  if (w.l2 < kSapB - 1) sap_send<2>(L.bw, w.t, f, U[2]);
-  if (w.l3 < kSapB - 1) sap_send<3>(L.bw, w.t, f, U[3]);
-}
-
-// acc = the in-block hops at the site of what its neighbours published.
-template <bool EO>
-__device__ __forceinline__ void sap_gather(const SapLds& L, const cx<float> (*U)[9], cx<float> acc[12]) {
-  const SapSite w = sap_site<EO>();
-#pragma unroll
-  for (int c = 0; c < 12; ++c) acc[c] = mk(0.f, 0.f);
-  sap_recv<0, EO>(L.rho, L.bw, w.s, w.q, w.l0, U[0], acc);
-  sap_recv<1, EO>(L.rho, L.bw, w.s, w.q, w.l1, U[1], acc);
-  sap_recv<2, EO>(L.rho, L.bw, w.s, w.q, w.l2, U[2], acc);
-  sap_recv<3, EO>(L.rho, L.bw, w.s, w.q, w.l3, U[3], acc);
 }
 
 // Block sums of (v, rho) and (v, v) over the workgroup (one barrier).
@@ -321,12 +141,14 @@ enum { SAP_FIRST = 0, SAP_MID = 1, SAP_LAST = 2 };
 
 // One half cycle on the blocks of `colour` (j = blockIdx.x; its partner is block
 // j of the other colour, the other block of the pair {2 k3, 2 k3 + 1} along x3).
-//   SAP_FIRST: x = 0 on entry, so r = eta, read from the even half field eta_e;
+//   SAP_FIRST: x = 0 on entry, so r = eta, read from the even half field eta_e
+//              (and the odd half eta_o when given, else eta is zero there);
 //              also writes the block-order eta of the block and of its partner
-//              (even sites) and zeroes the partner's x;
+//              and zeroes the partner's x;
 //   SAP_MID:   r = eta - D x from the block-order fields;
-//   SAP_LAST:  as SAP_MID, then writes the even sites of the block's x and of
-//              its partner's (final after this half cycle) to out_e.
+//   SAP_LAST:  as SAP_MID, then writes the block's x and its partner's (final
+//              after this half cycle) to out_e on even sites and, when given,
+//              to out_o on odd sites.
 // EO: even-odd preconditioned block solves (waves 0, 1 hold the even sites).
 template <int MODE, bool EO>
 __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int colour, int nmr,
@@ -335,7 +157,9 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
                                                            const float2* __restrict__ Vb,
                                                            const float4* __restrict__ Cb,
                                                            const float4* __restrict__ CIb,
-                                                           float4* __restrict__ out_e) {
+                                                           float4* __restrict__ out_e,
+                                                           const float4* __restrict__ eta_o,
+                                                           float4* __restrict__ out_o) {
   __shared__ SapLds L;
   const int j = blockIdx.x;
   int c0, c1, c2, c3;
@@ -366,11 +190,12 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
   }
   cx<float> rho[12];
   if (MODE == SAP_FIRST) {
-    if (q == 0) {
-      sp_load(eta_e, Ve, geo_half(g, x0, x1, x2, x3), rho);
+    if (q == 0 || eta_o) {
+      const float4* src = q ? eta_o : eta_e;
+      sp_load(src, Ve, geo_half(g, x0, x1, x2, x3), rho);
       sp_store(eb, kSapSites, t, rho);
       cx<float> ep[12];
-      sp_load(eta_e, Ve, geo_half(g, x0, x1, x2, x3p), ep);
+      sp_load(src, Ve, geo_half(g, x0, x1, x2, x3p), ep);
       sp_store(sap_blk<6>(Eb, Bp), kSapSites, t, ep);
     } else {
 #pragma unroll
@@ -393,7 +218,7 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
     sap_face<3, EO>(g, sb, x0, x1, x2, x3, w.l3, Xb, Vb, U[3], acc);
     cx<float> hx[12];
     sap_clover<kSapSites>(cb, xs, hx);
-    if (q == 0) {
+    if (q == 0 || eta_o) {
       sp_load(eb, kSapSites, t, rho);
     } else {
 #pragma unroll
@@ -432,7 +257,7 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
     // so a wave may publish right after it gathered.
 #pragma unroll
     for (int c = 0; c < 12; ++c) e[c] = q ? rho[c] : mk(0.f, 0.f);
-    if (MODE != SAP_FIRST) {
+    if (MODE != SAP_FIRST || eta_o) {
       // source of the Schur system: r_e - D_eo H_oo^-1 r_o = r_e + (1/2) hops(H_oo^-1 r_o)
       if (q == 1) {
         cx<float> so[12];
@@ -498,11 +323,12 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
     for (int c = 0; c < 12; ++c) e[c] = e[c] + xs[c];
   }
   sp_store(xb, kSapSites, t, e);
-  if (MODE == SAP_LAST && q == 0) {
-    sp_store(out_e, Ve, geo_half(g, x0, x1, x2, x3), e);
+  if (MODE == SAP_LAST && (q == 0 || out_o)) {
+    float4* dst = q ? out_o : out_e;
+    sp_store(dst, Ve, geo_half(g, x0, x1, x2, x3), e);
     cx<float> xp[12];
     sp_load(sap_blk<6>(Xb, Bp), kSapSites, t, xp);
-    sp_store(out_e, Ve, geo_half(g, x0, x1, x2, x3p), xp);
+    sp_store(dst, Ve, geo_half(g, x0, x1, x2, x3p), xp);
   }
 }
 
@@ -519,6 +345,8 @@ struct SapArgs {
   const float2* Vb;
   const float4 *Cb, *CIb;
   float4* out_e;
+  const float4* eta_o;
+  float4* out_o;
 };
 
 template <int MODE>
@@ -526,10 +354,10 @@ void sap_launch(bool eo, const SapArgs& a, int colour, hipStream_t s) {
   const dim3 grid(a.sb.nhalf), blk(kSapSites);
   if (eo)
     hipLaunchKernelGGL((k_sap_half<MODE, true>), grid, blk, 0, s, a.g, a.sb, colour, a.nmr, a.eta_e, a.Eb, a.Xb, a.Vb,
-                       a.Cb, a.CIb, a.out_e);
+                       a.Cb, a.CIb, a.out_e, a.eta_o, a.out_o);
   else
     hipLaunchKernelGGL((k_sap_half<MODE, false>), grid, blk, 0, s, a.g, a.sb, colour, a.nmr, a.eta_e, a.Eb, a.Xb,
-                       a.Vb, a.Cb, a.CIb, a.out_e);
+                       a.Vb, a.Cb, a.CIb, a.out_e, a.eta_o, a.out_o);
 }
 
 }  // namespace
@@ -544,33 +372,60 @@ bool sap_supported(const qxd_handle* h) {
   return g.cstar < 2 || (g.L1 / kSapB) % 2 == 0;
 }
 
+namespace {
+
+// The block-order copies of links and clover blocks for slot order eo (made
+// when the links, the clover blocks or the slot order changed since the last).
+qxd_status sap_pack(qxd_handle* h, int eo, float2** Vb, float4** Cb, float4** CIb, SapGeo* sb, hipStream_t s) {
+  const size_t V = (size_t)h->V;
+  *Vb = (float2*)ws_get(h, W_SAP_VB, V * 36 * sizeof(float2));
+  *Cb = (float4*)ws_get(h, W_SAP_CB, V * 18 * sizeof(float4));
+  *CIb = (float4*)ws_get(h, W_SAP_CIB, V / 2 * 18 * sizeof(float4));
+  if (!*Vb || !*Cb || !*CIb) return QXD_ENOMEM;
+  const Geo& g = h->geo;
+  const int nblk = (g.Le0 / kSapB) * (g.Le1 / kSapB) * (g.Le2 / kSapB) * (g.Le3 / kSapB);
+  *sb = SapGeo{g.Le1 / kSapB, g.Le2 / kSapB, g.Le3 / kSapB, nblk / 2};
+  // the copies are tagged 2 setup_gen + eo
+  const uint64_t tag = 2 * h->setup_gen + (uint64_t)eo;
+  if (h->sap_gen != tag) {
+    auto pack = eo ? k_sap_pack<true> : k_sap_pack<false>;
+    hipLaunchKernelGGL(pack, dim3(nblk), dim3(kSapSites), 0, s, g, *sb, reinterpret_cast<const float2*>(h->V32),
+                       reinterpret_cast<const float4*>(h->He32), reinterpret_cast<const float4*>(h->Ho32),
+                       reinterpret_cast<const float4*>(h->Hi32), *Vb, *Cb, *CIb);
+    QXD_HIP(hipGetLastError());
+    h->sap_gen = tag;
+  }
+  return QXD_OK;
+}
+
+}  // namespace
+
+qxd_status sap_blocks(qxd_handle* h, int eo, const float2** Vb, const float4** Cb, SapGeo* sb, hipStream_t s) {
+  if (!h->has_inverse) return QXD_ESTATE;
+  if (!sap_supported(h)) return QXD_EGEOM;
+  float2* vb;
+  float4 *cb, *cib;
+  QXD_TRY(sap_pack(h, eo, &vb, &cb, &cib, sb, s));
+  *Vb = vb;
+  *Cb = cb;
+  return QXD_OK;
+}
+
 qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, int eo, float4* out_e, const float4* in_e,
-                              hipStream_t s) {
+                              hipStream_t s, const float4* in_o, float4* out_o) {
   if (ncy < 1 || nmr < 1 || ncy > 64 || nmr > 64 || (eo != 0 && eo != 1)) return QXD_EINVAL;
   if (!h->has_inverse) return QXD_ESTATE;
   if (!sap_supported(h)) return QXD_EGEOM;
   const size_t V = (size_t)h->V;
-  float2* Vb = (float2*)ws_get(h, W_SAP_VB, V * 36 * sizeof(float2));
-  float4* Cb = (float4*)ws_get(h, W_SAP_CB, V * 18 * sizeof(float4));
-  float4* CIb = (float4*)ws_get(h, W_SAP_CIB, V / 2 * 18 * sizeof(float4));
+  float2* Vb;
+  float4 *Cb, *CIb;
+  SapGeo sb;
+  QXD_TRY(sap_pack(h, eo, &Vb, &Cb, &CIb, &sb, s));
   float4* Xb = (float4*)ws_get(h, W_SAP_XB, V * 6 * sizeof(float4));
   float4* Eb = (float4*)ws_get(h, W_SAP_EB, V * 6 * sizeof(float4));
-  if (!Vb || !Cb || !CIb || !Xb || !Eb) return QXD_ENOMEM;
+  if (!Xb || !Eb) return QXD_ENOMEM;
   const Geo& g = h->geo;
-  const int nblk = (g.Le0 / kSapB) * (g.Le1 / kSapB) * (g.Le2 / kSapB) * (g.Le3 / kSapB);
-  const SapGeo sb{g.Le1 / kSapB, g.Le2 / kSapB, g.Le3 / kSapB, nblk / 2};
-  // the copies are tagged 2 setup_gen + eo: repacked when the links, the clover
-  // blocks or the slot order changed since the last copy
-  const uint64_t tag = 2 * h->setup_gen + (uint64_t)eo;
-  if (h->sap_gen != tag) {
-    auto pack = eo ? k_sap_pack<true> : k_sap_pack<false>;
-    hipLaunchKernelGGL(pack, dim3(nblk), dim3(kSapSites), 0, s, g, sb, reinterpret_cast<const float2*>(h->V32),
-                       reinterpret_cast<const float4*>(h->He32), reinterpret_cast<const float4*>(h->Ho32),
-                       reinterpret_cast<const float4*>(h->Hi32), Vb, Cb, CIb);
-    QXD_HIP(hipGetLastError());
-    h->sap_gen = tag;
-  }
-  const SapArgs a{g, sb, nmr, in_e, Eb, Xb, Vb, Cb, CIb, out_e};
+  const SapArgs a{g, sb, nmr, in_e, Eb, Xb, Vb, Cb, CIb, out_e, in_o, out_o};
   for (int cy = 0; cy < ncy; ++cy)
     for (int colour = 0; colour < 2; ++colour) {
       if (cy == 0 && colour == 0)
@@ -588,4 +443,12 @@ extern "C" qxd_status qxd_sap_apply(qxd_handle* h, int ncy, int nmr, int eo, voi
                                     void* stream) {
   if (!h || !out_e || !in_e || out_e == in_e) return QXD_EINVAL;
   return sap_apply_internal(h, ncy, nmr, eo, (float4*)out_e, (const float4*)in_e, as_stream(stream));
+}
+
+extern "C" qxd_status qxd_sap_apply_full(qxd_handle* h, int ncy, int nmr, int eo, void* out, const void* in,
+                                         void* stream) {
+  if (!h || !out || !in || out == in) return QXD_EINVAL;
+  const size_t half = (size_t)6 * h->Ve;
+  return sap_apply_internal(h, ncy, nmr, eo, (float4*)out, (const float4*)in, as_stream(stream),
+                            (const float4*)in + half, (float4*)out + half);
 }

@@ -108,6 +108,8 @@ qxd_status cgnr(qxd_handle* h, InnerOp op, VT* x, VT* r, VT* p, VT* z, VT* w, si
 struct Precond {
   qxd_nn* net = nullptr;
   int sap_ncy = 0, sap_nmr = 0, sap_eo = 1;
+  qxd_dfl* dfl = nullptr;  // deflation: coarse correction, then SAP
+  int dfl_nc = 16;
   bool any() const { return net != nullptr || sap_ncy > 0; }
 };
 
@@ -116,6 +118,7 @@ qxd_status precond_apply(qxd_handle* h, const Precond& pc, VT* out, const VT* in
 template <>
 qxd_status precond_apply<float4>(qxd_handle* h, const Precond& pc, float4* out, const float4* in, hipStream_t s) {
   if (pc.net) return nn_apply_internal(h, pc.net, out, in, s);
+  if (pc.dfl) return dfl_apply_internal(h, pc.dfl, pc.dfl_nc, pc.sap_ncy, pc.sap_nmr, pc.sap_eo, out, in, s);
   return sap_apply_internal(h, pc.sap_ncy, pc.sap_nmr, pc.sap_eo, out, in, s);
 }
 template <>
@@ -384,8 +387,10 @@ extern "C" qxd_status qxd_solve_cg(qxd_handle* h, const qxd_solver_params* prm, 
   return rc;
 }
 
-extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm, qxd_nn* net, void* x,
-                                     const void* b, qxd_solver_stats* stats, void* stream) {
+namespace {
+
+qxd_status solve_fgcr(qxd_handle* h, const qxd_solver_params* prm, qxd_nn* net, qxd_dfl* dfl, void* x,
+                      const void* b, qxd_solver_stats* stats, void* stream) {
   auto t0 = clk::now();
   if (!h || !x || !b) return QXD_EINVAL;
   QXD_TRY(check_params(prm));
@@ -396,13 +401,16 @@ extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm
   if (mode < 0) return QXD_EINVAL;
   Precond pc;
   pc.net = net;
-  if (prm->sap_ncy > 0) {
-    if (net || prm->sap_nmr < 1) return QXD_EINVAL;  // one preconditioner at a time
+  if (prm->sap_ncy > 0 || dfl) {
+    if (net || prm->sap_ncy < 1 || prm->sap_nmr < 1) return QXD_EINVAL;  // one preconditioner at a time
     if (prm->sap_plain != 0 && prm->sap_plain != 1) return QXD_EINVAL;
+    if (prm->dfl_nc < 0 || prm->dfl_nc > QXD_DFL_MAXNC) return QXD_EINVAL;
     if (!sap_supported(h)) return QXD_EGEOM;
     pc.sap_ncy = prm->sap_ncy;
     pc.sap_nmr = prm->sap_nmr;
     pc.sap_eo = 1 - prm->sap_plain;
+    pc.dfl = dfl;
+    pc.dfl_nc = prm->dfl_nc > 0 ? prm->dfl_nc : 16;
   }
   if (mode == 0 && pc.any()) return QXD_EINVAL;  // the preconditioners run on FP32 vectors
   hipStream_t s = as_stream(stream);
@@ -486,6 +494,19 @@ extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm
   st.t_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
   if (stats) *stats = st;
   return rc;
+}
+
+}  // namespace
+
+extern "C" qxd_status qxd_solve_fgcr(qxd_handle* h, const qxd_solver_params* prm, qxd_nn* net, void* x,
+                                     const void* b, qxd_solver_stats* stats, void* stream) {
+  return solve_fgcr(h, prm, net, nullptr, x, b, stats, stream);
+}
+
+extern "C" qxd_status qxd_solve_fgcr_dfl(qxd_handle* h, const qxd_solver_params* prm, qxd_dfl* dfl, void* x,
+                                         const void* b, qxd_solver_stats* stats, void* stream) {
+  if (!dfl) return QXD_EINVAL;
+  return solve_fgcr(h, prm, nullptr, dfl, x, b, stats, stream);
 }
 
 // Training pairs from the method's own solves: plain FP64 GCR (restart 4, no
