@@ -17,8 +17,9 @@ Extra legs (not part of `value`): the time to a true FP64 residual 1e-10 of FP64
 CG against mixed-precision FGCR (and, when a trained network is available,
 network-preconditioned FGCR) on the same lattice; FP64 shifted normal solves
 (the paper's rational operator by multi-shift CG, twisted-mass systems solved
-together and one by one); and the FP64 CPU oracle timed on a bounded sample of
-even sites of the same lattice (`cpu_baseline`).
+together and one by one); inexactly deflated SAP-FGCR against SAP-FGCR, with
+matched and swapped-charge subspaces; and the FP64 CPU oracle timed on a
+bounded sample of even sites of the same lattice (`cpu_baseline`).
 """
 from __future__ import annotations
 
@@ -217,6 +218,8 @@ def main():
                                                args.nn_epochs, big, only)
         if not big and (not only or "shifted" in only):
             result["shifted_solves"] = shifted_leg(qxd, torch, lats, w, flavours)
+        if not big and (not only or "deflation" in only):
+            result["deflation"] = deflation_leg(qxd, torch, lats, w, flavours, U, A)
 
     if not args.no_cpu_baseline and not big:  # the oracle would hold 60 GB of host fields at 128 x 64^3
         log("cpu baseline (oracle) ...")
@@ -338,6 +341,75 @@ def shifted_leg(qxd, torch, lats, w, flavours):
         log("%s twisted-mass solves, mu %s: together %.1f ms, one by one %.1f ms" % (name, TM_MU, ms_all, ms_sep))
         del xs, y
         out[name] = res
+    return out
+
+
+DFL_NS, DFL_NIT, DFL_NC = 16, 10, 16  # subspace size, inverse-iteration rounds (4 SAP cycles of 4 steps), coarse steps
+LIGHT_KAPPA = 0.1405  # a lighter down-type quark for the deflation leg
+
+
+def deflation_leg(qxd, torch, lats, w, flavours, U, A):
+    """Inexactly deflated SAP-FGCR (DFL+SAP, FP32 inner, FP64 true residual 1e-10)
+    against SAP-FGCR with the same SAP settings: per flavour a subspace of
+    DFL_NS vectors from DFL_NIT rounds of SAP inverse iteration on seeded
+    Gaussian start vectors; then each physical flavour solved with the other
+    charge's subspace (the little operator rebuilt for its own operator); and a
+    lighter down-type quark (kappa LIGHT_KAPPA) where the low modes matter more."""
+    import synthgen as sg
+    out = {}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, st
+
+    light = dict(flavours[0])
+    light["kappa"] = LIGHT_KAPPA
+    lat_l = qxd.Lattice(w["L"], w["cstar"])
+    lat_l.setup(U, A, light)
+    cases = list(zip(lats, ("qhat-2", "qhat+4"))) + [(lat_l, "qhat-2 kappa %.4f" % LIGHT_KAPPA)]
+    b = sg.spinor(w["source_seed"] + 1, lats[0].V)
+    prm_sap = qxd.solver_params(res=1e-10, inner_prec=qxd.F32, sap_ncy=SAP_NCY, sap_nmr=SAP_NMR, sap_plain=SAP_PLAIN)
+    prm_dfl = qxd.solver_params(res=1e-10, inner_prec=qxd.F32, sap_ncy=SAP_NCY, sap_nmr=SAP_NMR, sap_plain=SAP_PLAIN,
+                                dfl_nc=DFL_NC)
+    dfls = []
+    for i, (lat, name) in enumerate(cases):
+        torch.cuda.empty_cache()
+        gen = torch.Generator(device="cuda").manual_seed(w["source_seed"] + 50 + i)
+        v = torch.randn(DFL_NS * 24 * lat.Ve, dtype=torch.complex64, device="cuda", generator=gen)
+        d = qxd.qxd_dfl_create(lat.h, DFL_NS)
+        ms_gen, _ = timed(lambda: qxd.qxd_dfl_generate(lat.h, d, v, DFL_NIT, 4, 4))
+        del v
+        dfls.append(d)
+        bd = lat.pack(torch.from_numpy(b).cuda())
+        x = lat.field(qxd.F64, full=True)
+        ms_s, st_s = timed(lambda: qxd.qxd_solve_fgcr(lat.h, prm_sap, None, x, bd, check=False))
+        ms_d, st_d = timed(lambda: qxd.qxd_solve_fgcr_dfl(lat.h, prm_dfl, d, x, bd, check=False))
+        out[name] = {"subspace_ms": round(ms_gen, 1), "ns": DFL_NS, "nit": DFL_NIT, "nc": DFL_NC,
+                     "sap_fgcr": {"ms": round(ms_s, 2), "iterations": st_s["inner_it"], "status": st_s["status"],
+                                  "true_residual": st_s["true_residual"]},
+                     "dfl_sap_fgcr": {"ms": round(ms_d, 2), "iterations": st_d["inner_it"], "status": st_d["status"],
+                                      "true_residual": st_d["true_residual"]}}
+        log("%s: subspace %.0f ms; SAP-FGCR %.1f ms (%d it), DFL+SAP-FGCR %.1f ms (%d it)" % (
+            name, ms_gen, ms_s, st_s["inner_it"], ms_d, st_d["inner_it"]))
+        del x, bd
+    # each physical flavour with the other charge's subspace
+    for i in (0, 1):
+        lat, name = cases[i]
+        other = dfls[1 - i]
+        qxd.qxd_dfl_little(lat.h, other)
+        bd = lat.pack(torch.from_numpy(b).cuda())
+        x = lat.field(qxd.F64, full=True)
+        ms, st = timed(lambda: qxd.qxd_solve_fgcr_dfl(lat.h, prm_dfl, other, x, bd, check=False))
+        out[name]["dfl_sap_fgcr_other_charge_subspace"] = {"ms": round(ms, 2), "iterations": st["inner_it"],
+                                                           "status": st["status"], "true_residual": st["true_residual"]}
+        log("%s with the other charge's subspace: %.1f ms (%d it)" % (name, ms, st["inner_it"]))
+        del x, bd
+    for d in dfls:
+        qxd.qxd_dfl_destroy(d)
+    lat_l.close()
     return out
 
 

@@ -256,7 +256,9 @@ qxd_status qxd_sap_apply_full(qxd_handle *h, int ncy, int nmr, int eo, void *out
 
 /* A deflation object for the handle's lattice: basis, little operator and work
  * fields (96 ns + 192 bytes per extended site and 72 ns^2 bytes per block);
- * ns in 1..QXD_DFL_MAXNS.  Destroy it before the handle. */
+ * ns in 1..QXD_DFL_MAXNS.  It may serve any handle of the same lattice
+ * (QXD_EINVAL for another lattice); the little operator belongs to the handle
+ * and operator it was last built with (qxd_dfl_generate, qxd_dfl_little). */
 qxd_status qxd_dfl_create(qxd_handle *h, int ns, qxd_dfl **d);
 qxd_status qxd_dfl_destroy(qxd_dfl *d);
 /* Build the subspace from ns start vectors v (FP32 full fields, contiguous,
@@ -271,7 +273,7 @@ qxd_status qxd_dfl_little(qxd_handle *h, qxd_dfl *d, void *stream);
 /* The preconditioner of the Schur system: out_e = (M (in_e, 0))_e with nc
  * coarse GCR steps (1..QXD_DFL_MAXNC) and ncy SAP cycles of nmr steps (eo as in
  * qxd_sap_apply); FP32 even half fields, distinct.  QXD_ESTATE when the little
- * operator was built for another operator than the handle's. */
+ * operator was built for another handle or an earlier operator of this one. */
 qxd_status qxd_dfl_apply(qxd_handle *h, qxd_dfl *d, int nc, int ncy, int nmr, int eo, void *out_e,
                          const void *in_e, void *stream);
 /* Basis vector k of every block as one FP32 full field (device). */

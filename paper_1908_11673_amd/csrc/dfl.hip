@@ -29,7 +29,9 @@
 struct qxd_dfl {
   int ns = 0, nblk = 0;
   SapGeo sb{};
-  uint64_t gen = 0;       // setup_gen of the operator A was built for (0: none)
+  Geo geo{};              // the lattice it was made for
+  const qxd_handle* op = nullptr;  // the handle whose operator A was built for
+  uint64_t gen = 0;       // that handle's setup_gen then (0: none)
   bool has_basis = false;
   float4* W = nullptr;    // [B][ns][6][256]
   float2* A = nullptr;    // [B][9][ns][ns]
@@ -427,6 +429,13 @@ qxd_status dfl_coarse(qxd_handle* h, qxd_dfl* d, int nc, hipStream_t s) {
   return QXD_OK;
 }
 
+// The handle's lattice must be the one the object was made for.
+bool dfl_same_lattice(const qxd_handle* h, const qxd_dfl* d) {
+  const Geo &a = h->geo, &b = d->geo;
+  return a.Le0 == b.Le0 && a.Le1 == b.Le1 && a.Le2 == b.Le2 && a.Le3 == b.Le3 && a.L1 == b.L1 && a.cstar == b.cstar &&
+         a.tanti == b.tanti;
+}
+
 qxd_status dfl_build_little(qxd_handle* h, qxd_dfl* d, hipStream_t s) {
   const float2* Vb;
   const float4* Cb;
@@ -435,6 +444,7 @@ qxd_status dfl_build_little(qxd_handle* h, qxd_dfl* d, hipStream_t s) {
   hipLaunchKernelGGL(k_dfl_little, dim3(d->nblk), dim3(kSapSites), 0, s, h->geo, d->sb, d->ns, d->W, Vb, Cb, d->nbr,
                      d->A);
   QXD_HIP(hipGetLastError());
+  d->op = h;
   d->gen = h->setup_gen;
   return QXD_OK;
 }
@@ -443,8 +453,8 @@ qxd_status dfl_build_little(qxd_handle* h, qxd_dfl* d, hipStream_t s) {
 
 qxd_status dfl_apply_internal(qxd_handle* h, qxd_dfl* d, int nc, int ncy, int nmr, int eo, float4* out_e,
                               const float4* in_e, hipStream_t s) {
-  if (nc < 1 || nc > kDflMaxNc) return QXD_EINVAL;
-  if (!d->has_basis || d->gen != h->setup_gen) return QXD_ESTATE;
+  if (nc < 1 || nc > kDflMaxNc || !dfl_same_lattice(h, d)) return QXD_EINVAL;
+  if (!d->has_basis || d->op != h || d->gen != h->setup_gen) return QXD_ESTATE;
   const Geo& g = h->geo;
   const size_t half = (size_t)6 * h->Ve;
   hipLaunchKernelGGL(k_dfl_restrict, dim3(d->nblk), dim3(kSapSites), 0, s, g, d->sb, d->ns, d->W, in_e,
@@ -468,6 +478,7 @@ extern "C" qxd_status qxd_dfl_create(qxd_handle* h, int ns, qxd_dfl** out) {
   if (!d) return QXD_ENOMEM;
   const Geo& g = h->geo;
   d->ns = ns;
+  d->geo = g;
   d->nblk = (g.Le0 / kSapB) * (g.Le1 / kSapB) * (g.Le2 / kSapB) * (g.Le3 / kSapB);
   d->sb = SapGeo{g.Le1 / kSapB, g.Le2 / kSapB, g.Le3 / kSapB, d->nblk / 2};
   const size_t V = (size_t)h->V, N = (size_t)d->nblk * ns;
@@ -505,7 +516,7 @@ extern "C" qxd_status qxd_dfl_destroy(qxd_dfl* d) {
 }
 
 extern "C" qxd_status qxd_dfl_generate(qxd_handle* h, qxd_dfl* d, void* v, int nit, int ncy, int nmr, void* stream) {
-  if (!h || !d || !v || nit < 0 || nit > 100) return QXD_EINVAL;
+  if (!h || !d || !v || nit < 0 || nit > 100 || !dfl_same_lattice(h, d)) return QXD_EINVAL;
   if (!h->has_inverse) return QXD_ESTATE;
   hipStream_t s = as_stream(stream);
   const size_t full = (size_t)12 * h->Ve, half = full / 2;
@@ -527,7 +538,7 @@ extern "C" qxd_status qxd_dfl_generate(qxd_handle* h, qxd_dfl* d, void* v, int n
 }
 
 extern "C" qxd_status qxd_dfl_little(qxd_handle* h, qxd_dfl* d, void* stream) {
-  if (!h || !d) return QXD_EINVAL;
+  if (!h || !d || !dfl_same_lattice(h, d)) return QXD_EINVAL;
   if (!d->has_basis || !h->has_inverse) return QXD_ESTATE;
   hipStream_t s = as_stream(stream);
   QXD_TRY(dfl_build_little(h, d, s));
@@ -543,7 +554,7 @@ extern "C" qxd_status qxd_dfl_apply(qxd_handle* h, qxd_dfl* d, int nc, int ncy, 
 }
 
 extern "C" qxd_status qxd_dfl_basis(qxd_handle* h, qxd_dfl* d, int k, void* out, void* stream) {
-  if (!h || !d || !out || k < 0 || k >= d->ns) return QXD_EINVAL;
+  if (!h || !d || !out || k < 0 || k >= d->ns || !dfl_same_lattice(h, d)) return QXD_EINVAL;
   if (!d->has_basis) return QXD_ESTATE;
   hipStream_t s = as_stream(stream);
   // the basis vector w_{B,k} of every block: W c with c = e_k on every block

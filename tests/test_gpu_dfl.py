@@ -142,6 +142,29 @@ def test_subspace_state_and_argument_errors(setup):
     assert lib.qxd_dfl_apply(lat.h, d, 4, 2, 3, 0, P(out), P(inp), None) == 0
 
 
+def test_dfl_belongs_to_its_lattice_and_operator(setup):
+    o, lat, d, *_ = setup
+    lib = qxd.load()
+    P = qxd._ptr
+    other = qxd.Lattice((8, 8, 8, 16), 2)
+    vp = 8 * 8 * 8 * 16
+    other.setup(sg.gauge_su3(2, 0.2, vp), sg.gauge_u1(2, 0.3, vp), sg.FLAVOURS["d"])
+    out, inp = other.field(qxd.F32), other.field(qxd.F32)
+    assert lib.qxd_dfl_apply(other.h, d, 4, 2, 3, 0, P(out), P(inp), None) == 1
+    assert lib.qxd_dfl_little(other.h, d, None) == 1
+    other.close()
+    twin = qxd.Lattice(lat.L, lat.cstar)
+    vp = int(np.prod(lat.L))
+    twin.setup(sg.gauge_su3(21, 0.2, vp), sg.gauge_u1(21, 0.3, vp), sg.FLAVOURS["d"])
+    out, inp = twin.field(qxd.F32), twin.field(qxd.F32)
+    assert lib.qxd_dfl_apply(twin.h, d, 4, 2, 3, 0, P(out), P(inp), None) == 8
+    qxd.qxd_dfl_little(twin.h, d)
+    assert lib.qxd_dfl_apply(twin.h, d, 4, 2, 3, 0, P(out), P(inp), None) == 0
+    assert lib.qxd_dfl_apply(lat.h, d, 4, 2, 3, 0, P(out), P(inp), None) == 8
+    qxd.qxd_dfl_little(lat.h, d)
+    twin.close()
+
+
 def test_dfl_rejects_lattices_sap_does_not_fit():
     lat = qxd.Lattice((8, 4, 8, 8), 3)
     U = sg.gauge_su3(1, 0.2, 8 * 4 * 8 * 8)
