@@ -278,7 +278,8 @@ qxd_status qxd_dfl_apply(qxd_handle *h, qxd_dfl *d, int nc, int ncy, int nmr, in
                          const void *in_e, void *stream);
 /* Basis vector k of every block as one FP32 full field (device). */
 qxd_status qxd_dfl_basis(qxd_handle *h, qxd_dfl *d, int k, void *out, void *stream);
-/* Copy the little operator (nblk * 9 * ns * ns complex64, [block][n][l][k]) and
+/* Copy the little operator (nblk * 9 * ns * ns complex64, [block][n][k][l]: entry
+ * (w_{block,l}, D w_{neighbour n,k})) and
  * the neighbour table (nblk * 9 ints; n = 0 the block, 1 + 2 mu its +mu and
  * 2 + 2 mu its -mu neighbour) to host memory.  Blocks are numbered colour-major
  * (all blocks of even block-coordinate parity first, x3 fastest). */

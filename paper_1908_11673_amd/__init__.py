@@ -356,7 +356,7 @@ def qxd_dfl_size(d):
 
 
 def qxd_dfl_little_get(d):
-    """(A as complex64 [nblk][9][ns][ns], nbr [nblk][9]) on the host."""
+    """(A as complex64 [nblk][9][ns][ns], [block][n][k][l], and nbr [nblk][9]) on the host."""
     nblk, ns = qxd_dfl_size(d)
     A = np.zeros((nblk, 9, ns, ns), dtype=np.complex64)
     nbr = np.zeros((nblk, 9), dtype=np.int32)

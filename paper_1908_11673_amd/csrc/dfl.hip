@@ -14,8 +14,10 @@
 //
 // Layout: W in block order (blocks colour-major as for SAP, plain slots), basis
 // vectors of a block contiguous: [B][k][6 float4 components][256 slots].  A is
-// [B][n][l][k] complex float, n = 0 the block itself, 1 + 2 mu its +mu
-// neighbour, 2 + 2 mu its -mu neighbour; nbr[B][n] names those blocks.  Coarse
+// [B][n][k][l] complex float (column k of the ns x ns block contiguous, so the
+// threads of the rows l of one block read consecutive words), n = 0 the block
+// itself, 1 + 2 mu its +mu neighbour, 2 + 2 mu its -mu neighbour; nbr[B][n]
+// names those blocks.  Coarse
 // vectors are [B][k] complex float.  One workgroup per block (one thread per
 // site) orthonormalises, builds A (the in-block part of D through the same LDS
 // exchange as SAP, the face hops by the face threads), restricts and prolongs.
@@ -34,7 +36,7 @@ struct qxd_dfl {
   uint64_t gen = 0;       // that handle's setup_gen then (0: none)
   bool has_basis = false;
   float4* W = nullptr;    // [B][ns][6][256]
-  float2* A = nullptr;    // [B][9][ns][ns]
+  float2* A = nullptr;    // [B][9][ns (k)][ns (l)]
   int* nbr = nullptr;     // [B][9]
   float2 *cb = nullptr, *cx = nullptr, *cr = nullptr;  // coarse source, solution, residual
   float2 *cz = nullptr, *cw = nullptr;                 // QXD_DFL_MAXNC coarse directions and their images
@@ -214,7 +216,7 @@ __device__ __forceinline__ void dfl_faces(const Geo& g, const SapGeo& sb, float2
       for (int c = 0; c < 12; ++c) hv[c] = -0.5f * hv[c];
       wl = W + (size_t)(bs / kSapSites) * bsz + (bs % kSapSites);
     }
-    dfl_project(red, wl, hv, ns, A + (((size_t)Bp * 9 + 2 + 2 * MU) * ns) * ns + k, ns);
+    dfl_project(red, wl, hv, ns, A + (((size_t)Bp * 9 + 2 + 2 * MU) * ns + k) * ns, 1);
   }
   {  // -MU: y = x - MU in B' = B - MU gets -(1/2) (1 - g_MU) U(y, MU) w(x)
     const int Bp = nbr[(size_t)9 * B + 2 + 2 * MU];
@@ -239,7 +241,7 @@ __device__ __forceinline__ void dfl_faces(const Geo& g, const SapGeo& sb, float2
       for (int c = 0; c < 12; ++c) hv[c] = -0.5f * hv[c];
       wl = W + (size_t)(bs / kSapSites) * bsz + (bs % kSapSites);
     }
-    dfl_project(red, wl, hv, ns, A + (((size_t)Bp * 9 + 1 + 2 * MU) * ns) * ns + k, ns);
+    dfl_project(red, wl, hv, ns, A + (((size_t)Bp * 9 + 1 + 2 * MU) * ns + k) * ns, 1);
   }
 }
 
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(kSapSites) void k_dfl_little(Geo g, SapGeo sb, int 
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[c] = v[c] - 0.5f * acc[c];
     // (the projections' barriers also separate these reads from the next publish)
-    dfl_project(red, wb + t, v, ns, A + ((size_t)B * 9 * ns) * ns + k, ns);
+    dfl_project(red, wb + t, v, ns, A + ((size_t)B * 9 * ns + k) * ns, 1);
     dfl_faces<0>(g, sb, red, B, x0, x1, x2, x3, l0, w, U[0], W, Vb, nbr, ns, k, A);
     dfl_faces<1>(g, sb, red, B, x0, x1, x2, x3, l1, w, U[1], W, Vb, nbr, ns, k, A);
     dfl_faces<2>(g, sb, red, B, x0, x1, x2, x3, l2, w, U[2], W, Vb, nbr, ns, k, A);
@@ -340,10 +342,10 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_dfl_cmv(int nblk, int ns, const f
   const int B = (int)(i / ns), l = (int)(i % ns);
   float re = 0.f, im = 0.f;
   for (int n = 0; n < 9; ++n) {
-    const float2* a = A + (((size_t)B * 9 + n) * ns + l) * ns;
+    const float2* a = A + ((size_t)B * 9 + n) * ns * ns + l;
     const float2* xv = x + (size_t)nbr[(size_t)9 * B + n] * ns;
     for (int k = 0; k < ns; ++k) {
-      const float2 av = a[k], xk = xv[k];
+      const float2 av = a[(size_t)k * ns], xk = xv[k];
       re += av.x * xk.x - av.y * xk.y;
       im += av.x * xk.y + av.y * xk.x;
     }

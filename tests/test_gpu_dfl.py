@@ -86,7 +86,7 @@ def test_little_operator_matches_the_oracle(setup):
         r = back[R]
         for n in range(9):
             c = back[int(nbr[R, n])]
-            dense[r * NS:(r + 1) * NS, c * NS:(c + 1) * NS] += Ag[R, n]
+            dense[r * NS:(r + 1) * NS, c * NS:(c + 1) * NS] += Ag[R, n].T  # stored [k][l]
     err = np.abs(dense - A).max() / np.abs(A).max()
     print("little operator: %.2e" % err)
     assert err < 1e-4
