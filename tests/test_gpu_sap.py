@@ -47,6 +47,19 @@ def test_sap_matches_the_oracle(pair, ncy, nmr, eo):
     assert np.abs(got[o.parity() == 1]).max() == 0
 
 
+@pytest.mark.parametrize("eo", [1, 0], ids=["eo", "plain"])
+def test_sap_on_full_fields_matches_the_oracle(pair, eo):
+    o, lat, blocks = pair
+    eta = sg.spinor(63, o.V)  # a source on both parities
+    out = lat.field(qxd.F32, full=True)
+    qxd.qxd_sap_apply_full(lat.h, 2, 3, eo, out, lat.pack(to_dev(eta), qxd.F32))
+    got = lat.unpack(out, qxd.F32).cpu().numpy()
+    want = osap.sap(o, eta, 2, 3, bool(eo), blocks)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print("full-field sap eo %d: rel err %.2e" % (eo, err))
+    assert err < 1e-6
+
+
 def test_sap_rejects_lattices_the_colouring_does_not_fit():
     lat = qxd.Lattice((8, 4, 8, 8), 3)  # C* in x2, x3 with L1 = 4: one block of shift
     U = sg.gauge_su3(1, 0.2, 8 * 4 * 8 * 8)
