@@ -96,3 +96,35 @@ def test_sap_fgcr_solves_to_1e10(pair, inner, sap_plain):
     assert st["sap_applies"] >= st["inner_it"] and st["inner_it"] < plain["inner_it"]
     res = np.linalg.norm(b - o.dirac(lat.unpack(x).cpu().numpy())) / np.linalg.norm(b)
     assert res <= 1e-10
+
+
+def test_sap_block_solves_at_64x32x32x32_leave_the_last_colour_nearly_solved():
+    """At the benchmark size, in the benchmark's launch configuration: after one
+    cycle whose block solves are nearly exact (40 steps), the residual
+    eta - D x on the blocks visited last is far below the residual on the
+    blocks visited first (a property of the cycle that holds at any size)."""
+    w = sg.WORKLOADS["c1"]
+    vp = int(np.prod(w["L"]))
+    lat = qxd.Lattice(w["L"], w["cstar"])
+    lat.setup(sg.gauge_su3(w["gauge_seed"], w["sigma_su3"], vp), sg.gauge_u1(w["gauge_seed"], w["sigma_u1"], vp), FD)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    eta = torch.randn(24 * lat.Ve, dtype=torch.complex64, device="cuda", generator=gen)
+    x = lat.field(qxd.F32, full=True)
+    qxd.qxd_sap_apply_full(lat.h, 1, 40, 0, x, eta)
+    dx = lat.field(qxd.F32, full=True)
+    qxd.qxd_dw_apply(lat.h, qxd.F32, dx, x)
+    r = (eta - dx).cpu().numpy()
+    lat.close()
+    # block colour of every site; within a parity the half index runs over the
+    # sites of that parity in lattice order (x3 fastest)
+    L0, L1, L2, L3 = w["L"][0], 2 * w["L"][1], w["L"][2], w["L"][3]
+    idx = np.indices((L0, L1, L2, L3)).reshape(4, -1)
+    colour = (idx // 4).sum(axis=0) & 1
+    par = idx.sum(axis=0) & 1
+    ve = L0 * L1 * L2 * L3 // 2
+    res = r.reshape(2, 6, ve, 2)  # [parity][float4 word][site][two complex components]
+    col = np.stack([colour[par == 0], colour[par == 1]])
+    last = np.sqrt(sum(np.sum(np.abs(res[p][:, col[p] == 1]) ** 2) for p in range(2)))
+    first = np.sqrt(sum(np.sum(np.abs(res[p][:, col[p] == 0]) ** 2) for p in range(2)))
+    print("residual on the colour solved last %.3e, first %.3e" % (last, first))
+    assert last < 1e-3 * first
