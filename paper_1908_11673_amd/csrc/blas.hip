@@ -54,6 +54,8 @@ __device__ inline double2 wsub(double2 a, double2 b) { return make_double2(a.x -
 __device__ inline float4 wsub(float4 a, float4 b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
 __device__ inline bool wfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 
+// Solver vectors are streamed once per kernel: loads and stores carry the
+// non-temporal hint (ld_stream, st_stream).
 #define GRID_STRIDE(i, n) for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
 
 // ---- kernels ---------------------------------------------------------------
@@ -73,7 +75,7 @@ template <class VT>
 __global__ __launch_bounds__(QXD_BLOCK) void k_norm2(const VT* __restrict__ x, size_t n, double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
   double a = 0.0;
-  GRID_STRIDE(i, n) a += wnorm2(x[i]);
+  GRID_STRIDE(i, n) a += wnorm2(ld_stream(&x[i]));
   double s = red_block(a, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_cdot(const VT* __restrict__ x, co
                                                     double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
   double re = 0.0, im = 0.0;
-  GRID_STRIDE(i, n) wcdot(x[i], y[i], re, im);
+  GRID_STRIDE(i, n) wcdot(ld_stream(&x[i]), ld_stream(&y[i]), re, im);
   double s = red_block(re, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
   s = red_block(im, sh);
@@ -99,9 +101,9 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_cg_xr(VT* __restrict__ x, VT* __r
   double alpha = scal[i_zz] / scal[i_ww];
   double a = 0.0;
   GRID_STRIDE(i, n) {
-    x[i] = wcaxpy(x[i], alpha, 0.0, p[i]);
-    VT rr = wcaxpy(r[i], -alpha, 0.0, w[i]);
-    r[i] = rr;
+    st_stream(&x[i], wcaxpy(ld_stream(&x[i]), alpha, 0.0, ld_stream(&p[i])));
+    VT rr = wcaxpy(ld_stream(&r[i]), -alpha, 0.0, ld_stream(&w[i]));
+    st_stream(&r[i], rr);
     a += wnorm2(rr);
   }
   double s = red_block(a, sh);
@@ -113,7 +115,7 @@ template <class VT>
 __global__ __launch_bounds__(QXD_BLOCK) void k_cg_p(VT* __restrict__ p, const VT* __restrict__ z, size_t n,
                                                     const double* __restrict__ scal, int i_new, int i_old) {
   double beta = scal[i_new] / scal[i_old];
-  GRID_STRIDE(i, n) p[i] = wcaxpy(z[i], beta, 0.0, p[i]);
+  GRID_STRIDE(i, n) st_stream(&p[i], wcaxpy(ld_stream(&z[i]), beta, 0.0, ld_stream(&p[i])));
 }
 
 // r = b - w; partial |r|^2
@@ -124,8 +126,8 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_sub_norm(VT* __restrict__ r, cons
   __shared__ double sh[QXD_BLOCK / 64];
   double a = 0.0;
   GRID_STRIDE(i, n) {
-    VT v = wsub(b[i], w[i]);
-    r[i] = v;
+    VT v = wsub(ld_stream(&b[i]), ld_stream(&w[i]));
+    st_stream(&r[i], v);
     a += wnorm2(v);
   }
   double s = red_block(a, sh);
@@ -141,10 +143,10 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_mdot(Ptrs basis, int k, const VT*
 #pragma unroll
   for (int j = 0; j < QXD_MAXKV; ++j) re[j] = im[j] = 0.0;
   GRID_STRIDE(i, n) {
-    VT vi = v[i];
+    VT vi = ld_stream(&v[i]);
 #pragma unroll
     for (int j = 0; j < QXD_MAXKV; ++j)
-      if (j < k) wcdot(((const VT*)basis.p[j])[i], vi, re[j], im[j]);
+      if (j < k) wcdot(ld_stream(&((const VT*)basis.p[j])[i]), vi, re[j], im[j]);
   }
 #pragma unroll
   for (int j = 0; j < QXD_MAXKV; ++j) {
@@ -165,9 +167,9 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_mupdate(VT* __restrict__ v, Ptrs 
   __shared__ double sh[QXD_BLOCK / 64];
   double a = 0.0;
   GRID_STRIDE(i, n) {
-    VT vi = v[i];
-    for (int j = 0; j < k; ++j) vi = wcaxpy(vi, -coef[2 * j], -coef[2 * j + 1], ((const VT*)basis.p[j])[i]);
-    v[i] = vi;
+    VT vi = ld_stream(&v[i]);
+    for (int j = 0; j < k; ++j) vi = wcaxpy(vi, -coef[2 * j], -coef[2 * j + 1], ld_stream(&((const VT*)basis.p[j])[i]));
+    st_stream(&v[i], vi);
     a += wnorm2(vi);
   }
   double s = red_block(a, sh);
@@ -183,9 +185,9 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_scale_cdot(VT* __restrict__ v, co
   double sc = 1.0 / sqrt(scal[i_n2]);
   double re = 0.0, im = 0.0;
   GRID_STRIDE(i, n) {
-    VT vi = wscale(v[i], sc);
-    v[i] = vi;
-    wcdot(vi, r[i], re, im);
+    VT vi = wscale(ld_stream(&v[i]), sc);
+    st_stream(&v[i], vi);
+    wcdot(vi, ld_stream(&r[i]), re, im);
   }
   double s = red_block(re, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -202,8 +204,8 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_r_update(VT* __restrict__ r, cons
   double cr = scal[i_c], ci = scal[i_c + 1];
   double a = 0.0;
   GRID_STRIDE(i, n) {
-    VT ri = wcaxpy(r[i], -cr, -ci, v[i]);
-    r[i] = ri;
+    VT ri = wcaxpy(ld_stream(&r[i]), -cr, -ci, ld_stream(&v[i]));
+    st_stream(&r[i], ri);
     a += wnorm2(ri);
   }
   double s = red_block(a, sh);
@@ -215,9 +217,9 @@ template <class VT>
 __global__ __launch_bounds__(QXD_BLOCK) void k_multi_axpy(VT* __restrict__ x, Ptrs basis, int k,
                                                           const double* __restrict__ coef, size_t n) {
   GRID_STRIDE(i, n) {
-    VT xi = x[i];
-    for (int j = 0; j < k; ++j) xi = wcaxpy(xi, coef[2 * j], coef[2 * j + 1], ((const VT*)basis.p[j])[i]);
-    x[i] = xi;
+    VT xi = ld_stream(&x[i]);
+    for (int j = 0; j < k; ++j) xi = wcaxpy(xi, coef[2 * j], coef[2 * j + 1], ld_stream(&((const VT*)basis.p[j])[i]));
+    st_stream(&x[i], xi);
   }
 }
 

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_schur1(Geo g, const SPT* __restri
   cx<T> acc[12], out[12];
   hop_site<DAG, T>(g, 1, h, in_e, Vo_l, Ve_l, acc);
   clover_mul<T>(Hi, g.Ve, h, acc, out);
-  sp_store(t_o, g.Ve, h, out);
+  sp_store_nt(t_o, g.Ve, h, out);
 }
 
 // pass 2: out_e = H_e psi_e - (1/4) g5? hop_eo(t_o); optional block partials of |out|^2
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_schur2(Geo g, const SPT* __restri
     clover_mul<T>(He, g.Ve, h, s, c);
 #pragma unroll
     for (int k = 0; k < 12; ++k) c[k] = c[k] - T(0.25) * acc[k];
-    sp_store(out_e, g.Ve, h, c);
+    sp_store_nt(out_e, g.Ve, h, c);
     if (NORM) n2 = sp_norm2(c);
   }
   if (NORM) {

@@ -126,11 +126,11 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_ms_r(double2* __restrict__ r, con
   const double a = scal[MS_ALPHA], s0 = scal[MS_S0];
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const double2 wi = w[i], pi = p[i];
-    double2 ri = r[i];
+    const double2 wi = ld_stream(&w[i]), pi = ld_stream(&p[i]);
+    double2 ri = ld_stream(&r[i]);
     ri.x -= a * (wi.x + s0 * pi.x);
     ri.y -= a * (wi.y + s0 * pi.y);
-    r[i] = ri;
+    st_stream(&r[i], ri);
     acc += ri.x * ri.x + ri.y * ri.y;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
@@ -169,34 +169,34 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_ms_update(VecPtrs P, VecPtrs X, d
   __syncthreads();
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
-    const double2 ri = r[i];
+    const double2 ri = ld_stream(&r[i]);
     double2 yi = make_double2(0.0, 0.0);
-    if (ACC) yi = y[i];
+    if (ACC) yi = ld_stream(&y[i]);
     for (int j = 0; j < n; ++j) {
       const double flags = coef[3][j];
       if (flags == 0.0) continue;
-      double2 pj = pp[j][i];
+      double2 pj = ld_stream(&pp[j][i]);
       if (flags == 1.0 || flags == 3.0) {
         const double a = coef[0][j];
         if (ACC) {
           yi.x += a * pj.x;
           yi.y += a * pj.y;
         } else {
-          double2 xj = xp[j][i];
+          double2 xj = ld_stream(&xp[j][i]);
           xj.x += a * pj.x;
           xj.y += a * pj.y;
-          xp[j][i] = xj;
+          st_stream(&xp[j][i], xj);
         }
       }
       if (flags >= 2.0) {
         const double z = coef[1][j], b = coef[2][j];
         pj.x = z * ri.x + b * pj.x;
         pj.y = z * ri.y + b * pj.y;
-        pp[j][i] = pj;
+        st_stream(&pp[j][i], pj);
         if (j == base) acc += pj.x * pj.x + pj.y * pj.y;
       }
     }
-    if (ACC) y[i] = yi;
+    if (ACC) st_stream(&y[i], yi);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
