@@ -94,6 +94,17 @@ __global__ void k_dfl_nbr(Geo g, SapGeo sb, int nblk, int* __restrict__ nbr) {
   dfl_nb<3>(g, sb, x0, x1, x2, x3, o + 7);
 }
 
+// A site's 12 components of a basis vector (block order, stride kSapSites),
+// loaded with the non-temporal hint: the basis is streamed once per use.
+__device__ __forceinline__ void dfl_wload(const float4* w, cx<float> s[12]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const float4 v = ld_stream(w + (size_t)j * kSapSites);
+    s[2 * j] = mk(v.x, v.y);
+    s[2 * j + 1] = mk(v.z, v.w);
+  }
+}
+
 __device__ __forceinline__ double dfl_wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -170,6 +181,9 @@ __global__ __launch_bounds__(kSapSites) void k_dfl_orth(Geo g, SapGeo sb, int ns
 
 // dst[l * stride] = sum over the block of conj(w_l) . f, for l < ns; wl points
 // at the thread's slot of its block's first basis vector (null: contributes 0).
+// STREAM: the basis is read once (restriction), else it is read again by the
+// same workgroup (little operator) and stays cacheable.
+template <bool STREAM>
 __device__ __forceinline__ void dfl_project(float2 (*red)[kDflMaxNs], const float4* wl, const cx<float> f[12],
                                             int ns, float2* __restrict__ dst, size_t stride) {
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -177,7 +191,10 @@ __device__ __forceinline__ void dfl_project(float2 (*red)[kDflMaxNs], const floa
     double re = 0.0, im = 0.0;
     if (wl) {
       cx<float> w[12];
-      sp_load(wl + (size_t)l * 6 * kSapSites, kSapSites, 0, w);
+      if (STREAM)
+        dfl_wload(wl + (size_t)l * 6 * kSapSites, w);
+      else
+        sp_load(wl + (size_t)l * 6 * kSapSites, kSapSites, 0, w);
       dfl_cdot(w, f, re, im);
     }
     re = dfl_wave_sum(re);
@@ -216,7 +233,7 @@ __device__ __forceinline__ void dfl_faces(const Geo& g, const SapGeo& sb, float2
       for (int c = 0; c < 12; ++c) hv[c] = -0.5f * hv[c];
       wl = W + (size_t)(bs / kSapSites) * bsz + (bs % kSapSites);
     }
-    dfl_project(red, wl, hv, ns, A + (((size_t)Bp * 9 + 2 + 2 * MU) * ns + k) * ns, 1);
+    dfl_project<false>(red, wl, hv, ns, A + (((size_t)Bp * 9 + 2 + 2 * MU) * ns + k) * ns, 1);
   }
   {  // -MU: y = x - MU in B' = B - MU gets -(1/2) (1 - g_MU) U(y, MU) w(x)
     const int Bp = nbr[(size_t)9 * B + 2 + 2 * MU];
@@ -241,7 +258,7 @@ __device__ __forceinline__ void dfl_faces(const Geo& g, const SapGeo& sb, float2
       for (int c = 0; c < 12; ++c) hv[c] = -0.5f * hv[c];
       wl = W + (size_t)(bs / kSapSites) * bsz + (bs % kSapSites);
     }
-    dfl_project(red, wl, hv, ns, A + (((size_t)Bp * 9 + 1 + 2 * MU) * ns + k) * ns, 1);
+    dfl_project<false>(red, wl, hv, ns, A + (((size_t)Bp * 9 + 1 + 2 * MU) * ns + k) * ns, 1);
   }
 }
 
@@ -283,7 +300,7 @@ __global__ __launch_bounds__(kSapSites) void k_dfl_little(Geo g, SapGeo sb, int 
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[c] = v[c] - 0.5f * acc[c];
     // (the projections' barriers also separate these reads from the next publish)
-    dfl_project(red, wb + t, v, ns, A + ((size_t)B * 9 * ns + k) * ns, 1);
+    dfl_project<false>(red, wb + t, v, ns, A + ((size_t)B * 9 * ns + k) * ns, 1);
     dfl_faces<0>(g, sb, red, B, x0, x1, x2, x3, l0, w, U[0], W, Vb, nbr, ns, k, A);
     dfl_faces<1>(g, sb, red, B, x0, x1, x2, x3, l1, w, U[1], W, Vb, nbr, ns, k, A);
     dfl_faces<2>(g, sb, red, B, x0, x1, x2, x3, l2, w, U[2], W, Vb, nbr, ns, k, A);
@@ -307,7 +324,7 @@ __global__ __launch_bounds__(kSapSites) void k_dfl_restrict(Geo g, SapGeo sb, in
 #pragma unroll
     for (int k = 0; k < 12; ++k) f[k] = mk(0.f, 0.f);
   }
-  dfl_project(red, W + (size_t)B * ns * 6 * kSapSites + t, f, ns, c + (size_t)B * ns, 1);
+  dfl_project<true>(red, W + (size_t)B * ns * 6 * kSapSites + t, f, ns, c + (size_t)B * ns, 1);
 }
 
 // out = W c, both halves of an FP32 full field.
@@ -322,11 +339,12 @@ __global__ __launch_bounds__(kSapSites) void k_dfl_prolong(Geo g, SapGeo sb, int
   cx<float> o[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) o[k] = mk(0.f, 0.f);
+#pragma unroll 4
   for (int k = 0; k < ns; ++k) {
     const float2 ck = c[(size_t)B * ns + k];
     const cx<float> a = mk(ck.x, ck.y);
     cx<float> w[12];
-    sp_load(wb + (size_t)k * 6 * kSapSites, kSapSites, 0, w);
+    dfl_wload(wb + (size_t)k * 6 * kSapSites, w);
 #pragma unroll
     for (int m = 0; m < 12; ++m) o[m] = o[m] + a * w[m];
   }
