@@ -1,0 +1,151 @@
+"""Inexact deflation at full size: the 32^3 x 64 physical lattice with C* in
+three directions (extended 64 x 64 x 32 x 32, 16,384 blocks of 4^4), with the
+subspace and solver settings the benchmark times (16 vectors, 10 rounds of SAP
+inverse iteration of 4 cycles x 4 steps; FGCR with SAP 2 cycles x 8 plain steps
+and 16 coarse GCR steps).  The oracle cannot repeat the subspace generation at
+this size, so the checks are properties that hold for any basis, computed in
+FP64 on the host from the GPU's FP32 basis on sampled blocks: each block's basis
+is orthonormal; the blocks that D w_{C,k} reaches are C and the face neighbours
+the GPU's table lists; the little operator's entries equal (w_{R,l}, D w_{C,k})
+with D the oracle's; and the deflated solve reaches the FP64 true residual 1e-10,
+checked by the oracle's D on sampled sites."""
+import numpy as np
+import pytest
+
+import oracle
+import synthgen as sg
+from tests.gpu_common import to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+qxd = pytest.importorskip("paper_1908_11673_amd")
+
+W = sg.WORKLOADS["c1"]
+NS, NIT, NC = 16, 10, 16
+
+
+def block_sites(o, B):
+    """Oracle site numbers of the GPU's block B (blocks numbered colour-major,
+    x3 fastest within a colour; every block count is even)."""
+    nb = [o.Le[m] // 4 for m in range(4)]
+    nhalf = int(np.prod(nb)) // 2
+    colour, j = divmod(B, nhalf)
+    c3h = j % (nb[3] // 2)
+    q = j // (nb[3] // 2)
+    c2 = q % nb[2]
+    q //= nb[2]
+    c1 = q % nb[1]
+    c0 = q // nb[1]
+    c3 = 2 * c3h + ((colour + c0 + c1 + c2) & 1)
+    l = np.stack(np.meshgrid(*[np.arange(4)] * 4, indexing="ij"), axis=-1).reshape(-1, 4)
+    return o.site(l + 4 * np.array([c0, c1, c2, c3]))
+
+
+def gpu_block(o, x):
+    """GPU block number of the block holding extended coordinates x."""
+    nb = [o.Le[m] // 4 for m in range(4)]
+    c = np.asarray(x) // 4
+    colour = int(c.sum()) & 1
+    j = ((c[0] * nb[1] + c[1]) * nb[2] + c[2]) * (nb[3] // 2) + c[3] // 2
+    return colour * (int(np.prod(nb)) // 2) + int(j)
+
+
+@pytest.fixture(scope="module")
+def full():
+    flav = sg.FLAVOURS["d"]
+    L = W["L"]
+    vphys = int(np.prod(L))
+    U = sg.gauge_su3(W["gauge_seed"], W["sigma_su3"], vphys)
+    A = sg.gauge_u1(W["gauge_seed"], W["sigma_u1"], vphys)
+    o = oracle.Oracle(L, W["cstar"])
+    o.set_gauge_physical(U, A)
+    o.set_flavour(**flav, cache=False, blocks=False)
+    lat = qxd.Lattice(L, W["cstar"])
+    lat.setup(U, A, flav)
+    del U, A
+    gen = torch.Generator(device="cuda").manual_seed(W["source_seed"] + 50)
+    v = torch.randn(NS * 24 * lat.Ve, dtype=torch.complex64, device="cuda", generator=gen)
+    d = qxd.qxd_dfl_create(lat.h, NS)
+    qxd.qxd_dfl_generate(lat.h, d, v, NIT, 4, 4)
+    del v
+    # sampled blocks: the origin's (every boundary crossing starts there), the
+    # far corner's, one on the C* mirror line x1 = L1, two at random
+    rng = np.random.default_rng(11)
+    xs = [(0, 0, 0, 0), (o.Le[0] - 1, o.Le[1] - 1, o.Le[2] - 1, o.Le[3] - 1), (8, o.L[1], 12, 28)]
+    blocks = [gpu_block(o, x) for x in xs] + [int(b) for b in rng.choice(o.V // 256, 2, replace=False)]
+    Ag, nbr = qxd.qxd_dfl_little_get(d)
+    wanted = sorted({int(r) for b in blocks for r in nbr[b]})
+    sites = {b: block_sites(o, b) for b in wanted}
+    basis = {b: np.zeros((NS, 256, 4, 3), dtype=np.complex128) for b in wanted}
+    out = lat.field(qxd.F32, full=True)
+    for k in range(NS):
+        qxd.qxd_dfl_basis(lat.h, d, k, out)
+        w = lat.unpack(out, qxd.F32)
+        for b in wanted:
+            basis[b][k] = w[torch.from_numpy(sites[b]).cuda()].cpu().numpy()
+        del w
+    del out
+    torch.cuda.empty_cache()
+    yield o, lat, d, blocks, sites, basis, Ag, nbr
+    qxd.qxd_dfl_destroy(d)
+    lat.close()
+
+
+def test_sampled_block_bases_are_orthonormal(full):
+    o, lat, d, blocks, sites, basis, Ag, nbr = full
+    worst = 0.0
+    for b, Q in basis.items():
+        Q = Q.reshape(NS, -1)
+        worst = max(worst, np.abs(Q.conj() @ Q.T - np.eye(NS)).max())
+    print("max |W_B^+ W_B - 1| over %d blocks: %.2e" % (len(basis), worst))
+    assert worst < 1e-5
+
+
+def test_little_operator_rows_on_sampled_blocks(full):
+    o, lat, d, blocks, sites, basis, Ag, nbr = full
+    psi = np.zeros((o.V, 4, 3), dtype=np.complex128)
+    nb_sites, _ = o.neighbours()
+    worst, scale = 0.0, np.abs(Ag).max()
+    for C in blocks:
+        touched = [int(r) for r in nbr[C]]
+        where = np.concatenate([sites[r] for r in touched])
+        for k in (0, NS // 2, NS - 1):
+            psi[sites[C]] = basis[C][k]
+            y = o.dirac_sites(psi, where)
+            psi[sites[C]] = 0.0
+            # D w_{C,k} vanishes outside C and its face neighbours
+            off = 0
+            for r in touched:
+                yr = y[off:off + 256]
+                off += 256
+                assert np.abs(yr).max() > 0.0
+                want = basis[r].reshape(NS, -1).conj() @ yr.reshape(-1)  # (w_{r,l}, D w_{C,k}), l < NS
+                got = sum(Ag[r, n, k] for n in range(9) if int(nbr[r, n]) == C)
+                worst = max(worst, np.abs(got - want).max())
+        # the blocks holding a neighbour of a site of C are exactly C's table
+        reach = {gpu_block(o, o.coords(s)) for s in nb_sites[sites[C]].reshape(-1)} | {C}
+        assert reach == set(touched), (C, sorted(reach), sorted(touched))
+    print("little operator: max |A_gpu - (w, D w)| / max |A| = %.2e" % (worst / scale))
+    assert worst < 1e-4 * scale
+
+
+def test_deflated_solve_reaches_1e10(full):
+    o, lat, d, *_ = full
+    b = sg.spinor(W["source_seed"] + 1, lat.V)
+    bd = lat.pack(to_dev(b))
+    base = dict(res=1e-10, inner_prec=qxd.F32, sap_ncy=2, sap_nmr=8, sap_plain=1)
+    x_sap = lat.field(qxd.F64, full=True)
+    st_s = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(**base), None, x_sap, bd)
+    x = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_fgcr_dfl(lat.h, qxd.solver_params(dfl_nc=NC, **base), d, x, bd)
+    print("FGCR steps: SAP %d, DFL+SAP %d" % (st_s["inner_it"], st["inner_it"]))
+    assert st["status"] == 0 and st["true_residual"] <= 1e-10
+    assert st["inner_it"] < st_s["inner_it"]
+    xs, xd = lat.unpack(x_sap), lat.unpack(x)
+    assert float(torch.linalg.norm(xd - xs) / torch.linalg.norm(xs)) <= 1e-6
+    sites = np.random.default_rng(12).choice(o.V, 256, replace=False)
+    dx = o.dirac_sites(xd.cpu().numpy(), sites)
+    res = np.linalg.norm(b[sites] - dx) / np.linalg.norm(b[sites])
+    print("oracle residual on 256 sampled sites: %.2e" % res)
+    assert res <= 1e-9
