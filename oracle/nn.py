@@ -100,3 +100,52 @@ def loss_and_grad(o, W, rs, es, kind=0, skip=0.0):
         for k, g in enumerate(backward(o, W, acts, gy)):
             grads[k] += g
     return L, grads
+
+
+def _patch_conv(Wl, h):
+    """One layer on a (n+2)^4 patch of sites: the (n)^4 interior outputs,
+    out[a] = sum_d W[tap(d)] h[a + 1 + d]."""
+    n = h.shape[0] - 2
+    out = np.zeros((n, n, n, n, Wl.shape[1]), dtype=np.float64)
+    for tap in range(81):
+        d = (tap // 27 - 1, (tap // 9) % 3 - 1, (tap // 3) % 3 - 1, tap % 3 - 1)
+        sl = h[1 + d[0]:1 + d[0] + n, 1 + d[1]:1 + d[1] + n, 1 + d[2]:1 + d[2] + n, 1 + d[3]:1 + d[3] + n]
+        out += sl @ Wl[tap].T
+    return out
+
+
+def forward_sites(o, W, r, sites, skip=0.0, nb=None):
+    """N(r) + skip r at the given sites only, as an (n, 4, 3) array.
+
+    The three layers reach three sites in every direction, so each output
+    needs only the 7^4 patch of sites at offsets a in [-3, 3]^4 from it, each
+    reached by |a_mu| unit steps of the neighbour map per direction.  Within
+    the patch, the site at offset a + d is the tap offset d of the site at
+    offset a, because unit steps commute (a C* crossing moves x1 by L1 in
+    whichever order the steps are taken).  ``nb``: the neighbour table
+    ``o.neighbours()[0]``, if the caller already has it."""
+    if nb is None:
+        nb, _ = o.neighbours()
+    par = o.parity()
+    rr = np.asarray(r).reshape(o.V, 12)
+    offs = np.stack(np.meshgrid(*[np.arange(-3, 4)] * 4, indexing="ij"), axis=-1).reshape(-1, 4)
+    out = np.zeros((len(sites), 4, 3), dtype=np.complex128)
+    for i, s in enumerate(np.asarray(sites)):
+        if par[s] == 1:
+            continue
+        P = np.full(len(offs), int(s), dtype=np.int64)
+        for mu in range(4):
+            for step in range(1, 4):
+                fw, bw = offs[:, mu] >= step, offs[:, mu] <= -step
+                P[fw] = nb[P[fw], mu, 0]
+                P[bw] = nb[P[bw], mu, 1]
+        P = P.reshape(7, 7, 7, 7)
+        h0 = np.zeros((7, 7, 7, 7, 24), dtype=np.float64)
+        h0[..., 0::2] = rr[P].real
+        h0[..., 1::2] = rr[P].imag
+        h0[par[P] == 1] = 0.0
+        h1 = np.maximum(_patch_conv(W[0], h0), 0.0)
+        h2 = np.maximum(_patch_conv(W[1], h1), 0.0)
+        y = _patch_conv(W[2], h2)[0, 0, 0, 0]
+        out[i] = (y[0::2] + 1j * y[1::2]).reshape(4, 3) + skip * rr[s].reshape(4, 3)
+    return out

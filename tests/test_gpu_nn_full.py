@@ -1,0 +1,80 @@
+"""The learned preconditioner at full size: the network applied on the 32^3 x
+64 physical lattice with C* in three directions (extended 64 x 64 x 32 x 32),
+the launch the benchmark's network-preconditioned solve makes (block-tiled
+convolution, persistent workgroups walking 8,192 blocks of 4 x 4 x 4 x 8),
+checked on sampled even sites against the FP64 network oracle evaluated site by
+site on the same weights rounded to bfloat16 (the bar of the small-lattice
+tests, 2e-2 in norm, for the bf16 operands and activations)."""
+import numpy as np
+import pytest
+
+import oracle
+import synthgen as sg
+from oracle import nn as onn
+from tests.gpu_common import to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+qxd = pytest.importorskip("paper_1908_11673_amd")
+
+W = sg.WORKLOADS["c1"]
+SHAPES = [(24, 32), (32, 32), (32, 24)]
+
+
+def init_weights(seed):
+    return [sg.gaussian(seed, k, np.sqrt(2.0 / (81 * ci)), 81 * co * ci).reshape(81, co, ci)
+            for k, (ci, co) in enumerate(SHAPES)]
+
+
+def bf16_round(a):
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def full():
+    L = W["L"]
+    vphys = int(np.prod(L))
+    U = sg.gauge_su3(W["gauge_seed"], W["sigma_su3"], vphys)
+    A = sg.gauge_u1(W["gauge_seed"], W["sigma_u1"], vphys)
+    lat = qxd.Lattice(L, W["cstar"])
+    lat.setup(U, A, sg.FLAVOURS["d"])
+    del U, A
+    o = oracle.Oracle(L, W["cstar"])
+    nb, _ = o.neighbours()
+    par = o.parity()
+    even = np.nonzero(par == 0)[0]
+    corners = o.site(np.array([[0, 0, 0, 0], [o.Le[0] - 1, o.Le[1] - 1, 0, 0], [0, o.L[1], o.Le[2] - 1, 1],
+                               [1, o.L[1] - 1, 0, o.Le[3] - 1], [o.Le[0] - 1, 0, o.Le[2] - 1, o.Le[3] - 2],
+                               [2, o.Le[1] - 1, 1, o.Le[3] - 1]]))
+    sites = np.concatenate([corners[par[corners] == 0], np.random.default_rng(3).choice(even, 64, replace=False)])
+    yield o, lat, nb, sites
+    lat.close()
+
+
+@pytest.mark.parametrize("skip", [0.0, 0.27])
+def test_network_apply_full_size_sampled(full, skip):
+    o, lat, nb, sites = full
+    ws = init_weights(5)
+    net = qxd.qxd_nn_create(lat.h)
+    qxd.qxd_nn_set_weights(net, np.concatenate([w.reshape(-1) for w in ws]).astype(np.float32))
+    qxd.qxd_nn_set_skip(net, skip)
+    r = sg.spinor(W["source_seed"] + 7, o.V)
+    r[o.parity() == 1] = 0
+    out = lat.field(qxd.F32)
+    qxd.qxd_nn_apply(lat.h, net, out, lat.pack(to_dev(r), qxd.F32)[:12 * lat.Ve].clone())
+    full_out = lat.field(qxd.F32, full=True)
+    full_out[:12 * lat.Ve] = out
+    got = lat.unpack(full_out, qxd.F32)[torch.from_numpy(sites).cuda()].cpu().numpy()
+    qxd.qxd_nn_destroy(net)
+    n = np.linalg.norm(r)
+    want = n * onn.forward_sites(o, [bf16_round(w) for w in ws], r / n, sites, skip, nb=nb)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    # no single site far off either, measured against the sampled sites' rms output
+    rms = np.linalg.norm(want) / np.sqrt(len(sites))
+    worst = np.linalg.norm((got - want).reshape(len(sites), -1), axis=1).max() / rms
+    print("skip %.2f: %d sampled sites, rel err %.2e, worst site %.2e of the rms" % (skip, len(sites), err, worst))
+    assert err < 2e-2
+    assert worst < 5e-2

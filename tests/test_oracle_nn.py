@@ -93,3 +93,18 @@ def test_network_is_positively_homogeneous_and_translation_equivariant():
     perm = nb[nb[:, 0, 1], 0, 1]
     yt, _ = nn.forward(o, W, r[perm])
     assert np.abs(yt - y[perm]).max() < 1e-13 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("L,cstar", [((4, 4, 4, 8), 3), ((8, 4, 4, 4), 1), ((2, 4, 2, 6), 2)])
+def test_site_local_forward_equals_the_whole_lattice_forward(L, cstar):
+    """The patch evaluation used for sampled outputs at full size reproduces
+    the whole-lattice network at every site (patches wider than the lattice
+    included: extents 2 and 4 wrap inside the 7^4 patch)."""
+    o = lattice(L, cstar)
+    W = weights(13, scale=2.0)
+    r = sg.spinor(6, o.V)
+    r[o.parity() == 1] = 0
+    y, _ = nn.forward(o, W, r, skip=0.3)
+    sites = np.arange(o.V) if o.V <= 1024 else np.random.default_rng(1).choice(o.V, 300, replace=False)
+    ys = nn.forward_sites(o, W, r, sites, skip=0.3)
+    assert np.abs(ys - y[sites]).max() <= 1e-13 * np.abs(y).max()
