@@ -280,7 +280,8 @@ def copy_calibration(torch):
 # steps, the fastest of a sweep at 64 x 32^3.  The even-odd preconditioned block
 # solver (the paper's) needs fewer FGCR steps but costs twice as much per step
 # here (half the wavefronts wait in each of its two hop exchanges): 153 ms
-# against 128 ms at its best setting.
+# against 128 ms at its best setting.  The paper's own setting (5 cycles, 5
+# even-odd minimal-residual steps per block) is timed as a leg of its own.
 SAP_NCY, SAP_NMR, SAP_PLAIN = 2, 8, 1
 
 
@@ -460,7 +461,8 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, on
         legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16))]
         if not big:  # FGCR's 2 nkv direction vectors do not fit beside the 128 x 64^3 operator
             legs += [("fgcr_f32_in_f64", fgcr(qxd.F32)), ("fgcr_bf16links_in_f64", fgcr(qxd.BF16)),
-                     ("fgcr_f32_sap_in_f64", fgcr(qxd.F32, sap_ncy=SAP_NCY, sap_nmr=SAP_NMR, sap_plain=SAP_PLAIN))]
+                     ("fgcr_f32_sap_in_f64", fgcr(qxd.F32, sap_ncy=SAP_NCY, sap_nmr=SAP_NMR, sap_plain=SAP_PLAIN)),
+                     ("fgcr_f32_sap_eo55_in_f64", fgcr(qxd.F32, sap_ncy=5, sap_nmr=5, sap_plain=0))]
         if net is not None:
             legs.append(("fgcr_f32_nn_in_f64", fgcr(qxd.F32, net)))
         for tag, fn in legs:
