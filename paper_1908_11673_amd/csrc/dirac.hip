@@ -368,12 +368,15 @@ static void launch_schur(qxd_handle* h, int dagger, SPT* out, const SPT* in, SPT
 }
 
 // Workgroup walk for the Schur passes (site_tile): windows of K tiles per XCD.
-// Measured on the 64x64x32x32 lattice with non-temporal output stores: K = 8
-// is best for every precision (FP64 1.78 ms against 1.80 at K = 16).
+// Measured with non-temporal output stores, the same K for every precision:
+// with 128 tiles per time slice (64x64x32x32) K = 8 is best (FP64 1.78 ms
+// against 1.80 at K = 16), with 1024 (128x128x64x64) K = 16 (27.3-27.6 ms
+// against 28.1).
 static int walk_chunk(const qxd_handle* h, qxd_prec p) {
   (void)p;
   if (h->tchunk_env) return h->geo.tchunk;
-  return 8;
+  const int64_t tiles_per_slice = (int64_t)h->geo.L3h * h->geo.Le2 * h->geo.Le1 / QXD_BLOCK;
+  return tiles_per_slice >= 512 ? 16 : 8;
 }
 
 qxd_status qxd_schur_apply(qxd_handle* h, qxd_prec p, int dagger, void* out_e, const void* in_e, double* norm_slot,
