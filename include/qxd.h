@@ -197,7 +197,8 @@ qxd_status qxd_unpack(qxd_handle *h, qxd_prec p, double *aos, const void *soa, v
  * (r = bhat - D_hat x in FP64, x += |r| e) around an inner CG on the normal
  * equations whose operator and vectors are FP32 (BF16: links and spinors stored
  * in bfloat16), run to the relative residual max(inner_res, res |b| / (2 |r|)).
- * b, x: F64 full fields (device).  stats may be NULL. */
+ * b, x: F64 full fields (device).  stats may be NULL.  b = 0: x = 0, QXD_OK,
+ * no iteration, residual 0 (the same in every solver below). */
 qxd_status qxd_solve_cg(qxd_handle *h, const qxd_solver_params *params, void *x, const void *b,
                         qxd_solver_stats *stats, void *stream);
 
@@ -303,8 +304,8 @@ qxd_status qxd_dfl_size(const qxd_dfl *d, int *nblk, int *ns);
  * pointers to distinct FP64 even half fields (caller-owned, overwritten);
  * b_e: FP64 even half field, not one of x_e.  stats->inner_it: iterations;
  * stats->true_residual: the largest |b - (M + s_j) x_j| / |b| recomputed at the
- * end; stats->schur_applies: D_hat and D_hat^+ applications.  The library holds
- * nshift + 3 FP64 half fields of workspace.  QXD_EINVAL for nshift outside
+ * end; stats->schur_applies: D_hat and D_hat^+ applications.  b_e = 0: every
+ * x_e[j] = 0, QXD_OK.  The library holds nshift + 3 FP64 half fields of workspace.  QXD_EINVAL for nshift outside
  * 1..QXD_MS_MAXSHIFT, a negative or non-finite shift, aliased or NULL fields;
  * QXD_ESTATE before the clover inverse; QXD_ENOCONV when nmx iterations do not
  * reach res; QXD_ENAN on a non-finite residual. */
@@ -318,9 +319,9 @@ qxd_status qxd_solve_mscg(qxd_handle *h, const qxd_solver_params *prm, int nshif
  * solutions are summed as they converge (never stored).  A factor P_{k,l} of a
  * frequency-split approximation is the call with A = 1 and the sub-arrays
  * nu + k, mu + k, n = l - k + 1.  nu, mu: host arrays, the mu_j^2 distinct;
- * in_e, out_e: FP64 even half fields (may alias).  stats->true_residual: the
- * largest recurrence residual |zeta_j r| / |in| of the shifted systems at their
- * last update (not recomputed).  Errors as qxd_solve_mscg, and QXD_EINVAL for
+ * in_e, out_e: FP64 even half fields (may alias; in_e = 0 gives out_e = 0).
+ * stats->true_residual: the largest recurrence residual |zeta_j r| / |in| of the
+ * shifted systems at their last update (not recomputed).  Errors as qxd_solve_mscg, and QXD_EINVAL for
  * repeated mu_j^2. */
 qxd_status qxd_rational_apply(qxd_handle *h, const qxd_solver_params *prm, double A, int n, const double *nu,
                               const double *mu, void *out_e, const void *in_e, qxd_solver_stats *stats,

@@ -335,7 +335,20 @@ qxd_status ms_norm(qxd_handle* h, const double2* phi, double* nphi, hipStream_t 
   QXD_TRY(read_slots(h, MS_RR, 1, s));
   *nphi = std::sqrt(h->scal_host[MS_RR]);
   if (!std::isfinite(*nphi)) return QXD_ENAN;
-  if (*nphi == 0.0) return QXD_EINVAL;
+  return QXD_OK;
+}
+
+// phi = 0: every shifted solution, and R phi, vanish exactly; no iteration.
+qxd_status ms_zero(qxd_handle* h, int n, double2* const* out, qxd_solver_stats* stats, clk::time_point t0,
+                   hipStream_t s) {
+  for (int j = 0; j < n; ++j) blas_zero<double2>(out[j], (size_t)12 * h->Ve, s);
+  QXD_HIP(hipGetLastError());
+  QXD_HIP(hipStreamSynchronize(s));
+  qxd_solver_stats st{};
+  st.status = QXD_OK;
+  st.true_residual = 0.0;
+  st.t_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  if (stats) *stats = st;
   return QXD_OK;
 }
 
@@ -357,6 +370,7 @@ extern "C" qxd_status qxd_solve_mscg(qxd_handle* h, const qxd_solver_params* prm
   double nphi;
   QXD_TRY(ms_norm(h, phi, &nphi, s));
   double2* const* X = reinterpret_cast<double2* const*>(x_e);
+  if (nphi == 0.0) return ms_zero(h, nshift, X, stats, t0, s);
   qxd_status rc = ms_run(h, prm, nshift, shifts, nullptr, X, nullptr, phi, nphi, &st, s);
   if (rc == QXD_OK || rc == QXD_ENOCONV) {
     // true residuals |phi - (M + s_j) x_j| / |phi|, the largest reported
@@ -418,6 +432,10 @@ extern "C" qxd_status qxd_rational_apply(qxd_handle* h, const qxd_solver_params*
   qxd_solver_stats st{};
   double nphi;
   QXD_TRY(ms_norm(h, phi, &nphi, s));
+  if (nphi == 0.0) {
+    double2* o = (double2*)out_e;
+    return ms_zero(h, 1, &o, stats, t0, s);
+  }
   qxd_status rc = ms_run(h, prm, n, shifts.data(), sigma.data(), nullptr, y, phi, nphi, &st, s);
   if (rc == QXD_OK || rc == QXD_ENOCONV)
     hipLaunchKernelGGL(k_ms_finish, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, (double2*)out_e, phi, y, A, len);

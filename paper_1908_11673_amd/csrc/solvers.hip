@@ -43,12 +43,32 @@ qxd_status true_residual(qxd_handle* h, const double2* x, const double2* b, doub
   return QXD_OK;
 }
 
-qxd_status norm_full(qxd_handle* h, const double2* b, double* nb, hipStream_t s) {
+// |b| of a full field; QXD_ENAN if it is not finite.
+qxd_status norm_source(qxd_handle* h, const double2* b, double* nb, hipStream_t s) {
   blas_norm2<double2>(h, b, (size_t)24 * h->Ve, h->scal + S_NB, s);
   QXD_TRY(read_scal(h, S_NB, 1, s));
   *nb = std::sqrt(h->scal_host[S_NB]);
   if (!std::isfinite(*nb)) return QXD_ENAN;
+  return QXD_OK;
+}
+
+// As norm_source, with a vanishing b rejected (QXD_EINVAL).
+qxd_status norm_full(qxd_handle* h, const double2* b, double* nb, hipStream_t s) {
+  QXD_TRY(norm_source(h, b, nb, s));
   if (*nb == 0.0) return QXD_EINVAL;
+  return QXD_OK;
+}
+
+// b = 0: x = 0 solves D x = b exactly; no iteration, residual 0.
+qxd_status zero_solution(qxd_handle* h, void* x, qxd_solver_stats* stats, clk::time_point t0, hipStream_t s) {
+  blas_zero<double2>((double2*)x, (size_t)24 * h->Ve, s);
+  QXD_HIP(hipGetLastError());
+  QXD_HIP(hipStreamSynchronize(s));
+  qxd_solver_stats st{};
+  st.status = QXD_OK;
+  st.true_residual = 0.0;
+  st.t_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  if (stats) *stats = st;
   return QXD_OK;
 }
 
@@ -265,8 +285,9 @@ qxd_status solve_cg_dc(qxd_handle* h, const qxd_solver_params* prm, void* x, con
   if (!bh || !xe || !r || !w || !r32 || !e32 || !p32 || !z32 || !w32) return QXD_ENOMEM;
   qxd_solver_stats st{};
   double nb;
-  qxd_status rc = norm_full(h, (const double2*)b, &nb, s);
+  qxd_status rc = norm_source(h, (const double2*)b, &nb, s);
   if (rc != QXD_OK) return rc;
+  if (nb == 0.0) return zero_solution(h, x, stats, t0, s);
   const double tol = prm->res * nb;
   QXD_TRY(qxd_eo_source(h, bh, b, s));
   blas_zero<double2>(xe, n64, s);
@@ -331,8 +352,9 @@ extern "C" qxd_status qxd_solve_cg(qxd_handle* h, const qxd_solver_params* prm, 
   if (!bh || !xe || !r || !p || !z || !w) return QXD_ENOMEM;
   qxd_solver_stats st{};
   double nb;
-  qxd_status rc = norm_full(h, (const double2*)b, &nb, s);
+  qxd_status rc = norm_source(h, (const double2*)b, &nb, s);
   if (rc != QXD_OK) return rc;
+  if (nb == 0.0) return zero_solution(h, x, stats, t0, s);
   double tol = prm->res * nb;
   QXD_TRY(qxd_eo_source(h, bh, b, s));
   blas_zero<double2>(xe, n, s);
@@ -428,8 +450,9 @@ qxd_status solve_fgcr(qxd_handle* h, const qxd_solver_params* prm, qxd_nn* net, 
   }
   qxd_solver_stats st{};
   double nb;
-  qxd_status rc = norm_full(h, (const double2*)b, &nb, s);
+  qxd_status rc = norm_source(h, (const double2*)b, &nb, s);
   if (rc != QXD_OK) return rc;
+  if (nb == 0.0) return zero_solution(h, x, stats, t0, s);
   double tol = prm->res * nb;
   QXD_TRY(qxd_eo_source(h, bh, b, s));
   blas_zero<double2>(xe, n64, s);

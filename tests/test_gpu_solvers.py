@@ -149,3 +149,44 @@ def test_trim_keeps_the_operator_and_blocks_rebuilding():
     qxd.qxd_dw_eo_schur(lat.h, qxd.F64, 0, again, psi)
     assert torch.equal(before, again)
     lat.close()
+
+
+def test_zero_source_gives_the_zero_solution():
+    """The degenerate source b = 0: every solver returns x = 0 exactly, status
+    OK, no iteration and residual 0, whatever x held before (CG and FGCR in
+    every precision and with every preconditioner, the multi-shift solver and
+    the rational operator)."""
+    L, cstar = (8, 8, 8, 8), 3
+    o, lat, _ = make_pair(L, cstar, FD, sigma=0.2, su1=0.3, seed=23)
+    zero = lat.field(qxd.F64, full=True)
+    net = qxd.qxd_nn_create(lat.h)
+    qxd.qxd_nn_set_weights(net, np.full(qxd.NN_NWEIGHTS, 0.01, np.float32))
+    d = qxd.qxd_dfl_create(lat.h, 4)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    qxd.qxd_dfl_generate(lat.h, d, torch.randn(4 * 24 * lat.Ve, dtype=torch.complex64, device="cuda",
+                                               generator=gen), 2, 2, 3)
+    cases = [("cg f64", lambda x: qxd.qxd_solve_cg(lat.h, qxd.solver_params(inner_prec=qxd.F64), x, zero)),
+             ("cg f32", lambda x: qxd.qxd_solve_cg(lat.h, qxd.solver_params(inner_prec=qxd.F32), x, zero)),
+             ("cg bf16", lambda x: qxd.qxd_solve_cg(lat.h, qxd.solver_params(inner_prec=qxd.BF16), x, zero)),
+             ("fgcr f64", lambda x: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(inner_prec=qxd.F64), None, x, zero)),
+             ("fgcr f32", lambda x: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(inner_prec=qxd.F32), None, x, zero)),
+             ("fgcr nn", lambda x: qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(inner_prec=qxd.F32), net, x, zero)),
+             ("fgcr sap", lambda x: qxd.qxd_solve_fgcr(
+                 lat.h, qxd.solver_params(inner_prec=qxd.F32, sap_ncy=2, sap_nmr=4), None, x, zero)),
+             ("fgcr dfl", lambda x: qxd.qxd_solve_fgcr_dfl(
+                 lat.h, qxd.solver_params(inner_prec=qxd.F32, sap_ncy=2, sap_nmr=4, dfl_nc=4), d, x, zero))]
+    for tag, solve in cases:
+        x = torch.ones(24 * lat.Ve, dtype=torch.complex128, device="cuda")
+        st = solve(x)
+        assert st["status"] == 0 and st["inner_it"] == 0 and st["true_residual"] == 0.0, (tag, st)
+        assert int(torch.count_nonzero(x)) == 0, tag
+    ze = lat.field(qxd.F64)
+    xs = [torch.ones(12 * lat.Ve, dtype=torch.complex128, device="cuda") for _ in range(3)]
+    st = qxd.qxd_solve_mscg(lat.h, qxd.solver_params(), [0.0, 0.01, 0.1], xs, ze)
+    assert st["status"] == 0 and st["inner_it"] == 0 and all(int(torch.count_nonzero(x)) == 0 for x in xs)
+    out = torch.ones(12 * lat.Ve, dtype=torch.complex128, device="cuda")
+    st = qxd.qxd_rational_apply(lat.h, qxd.solver_params(), 0.5, [0.1, 0.3], [0.2, 0.4], out, ze)
+    assert st["status"] == 0 and int(torch.count_nonzero(out)) == 0
+    qxd.qxd_dfl_destroy(d)
+    qxd.qxd_nn_destroy(net)
+    lat.close()
