@@ -1,0 +1,86 @@
+"""Maximum size: the largest one-GPU share, 64^3 x 128 physical with C* in
+three directions (extended 128 x 128 x 64 x 64, 67,108,864 sites; the FP64,
+FP32 and bf16 copies of the operator take about 175 GB of the GPU), up-type
+flavour.  The Schur operator in the launch configuration the benchmark times
+at this size (windows of 16 tiles per XCD), checked against the oracle on
+sampled even sites, including the lattice corners where every C* crossing
+happens; FP64 to 1e-13, FP32 to 1e-6."""
+import numpy as np
+import pytest
+
+import oracle
+import synthgen as sg
+from tests.gpu_common import to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+qxd = pytest.importorskip("paper_1908_11673_amd")
+
+W = sg.WORKLOADS["c4"]
+
+
+@pytest.fixture(scope="module")
+def biggest():
+    flav = sg.FLAVOURS["u"]
+    L = W["L"]
+    vphys = int(np.prod(L))
+    print("generating %s fields" % (L,), flush=True)
+    U = sg.gauge_su3(W["gauge_seed"], W["sigma_su3"], vphys)
+    A = sg.gauge_u1(W["gauge_seed"], W["sigma_u1"], vphys)
+    o = oracle.Oracle(L, W["cstar"])
+    o.set_gauge_physical(U, A)
+    o.set_flavour(**flav, cache=False, blocks=False)
+    lat = qxd.Lattice(L, W["cstar"])
+    st = lat.setup(U, A, flav)
+    print("clover min pivot %.4f" % st["min_pivot"], flush=True)
+    del U, A
+    psi = sg.spinor(W["source_seed"], o.V)
+    psi[o.parity() == 1] = 0
+    yield o, lat, psi
+    lat.close()
+    torch.cuda.empty_cache()
+
+
+def _sample(o, n=128, seed=0):
+    even = np.nonzero(o.parity() == 0)[0]
+    rng = np.random.default_rng(seed)
+    s = rng.choice(even, size=n - 8, replace=False)
+    corners = o.site(np.array([[0, 0, 0, 0], [o.Le[0] - 1, o.Le[1] - 1, 0, 0], [0, o.L[1] - 1, o.Le[2] - 1, 1],
+                               [1, o.L[1], 0, o.Le[3] - 1], [o.Le[0] - 1, 0, o.Le[2] - 1, o.Le[3] - 1],
+                               [0, o.Le[1] - 1, 1, 0], [1, 0, 0, 0], [0, 1, o.Le[2] - 1, o.Le[3] - 2]]))
+    corners = corners[o.parity()[corners] == 0]
+    return np.concatenate([corners, s])
+
+
+def _apply(lat, psi, prec, dagger, sites):
+    """D_hat (psi) on the GPU, returned at the sampled sites only."""
+    x = lat.pack(to_dev(psi), prec)
+    out = lat.field(prec, full=True)
+    qxd.qxd_dw_eo_schur(lat.h, prec, dagger, out[:out.numel() // 2], x[:x.numel() // 2])
+    del x
+    got = lat.unpack(out, prec)[torch.from_numpy(sites).cuda()].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    return got
+
+
+@pytest.mark.parametrize("dagger", [False, True])
+def test_schur_f64_max_size_sampled(biggest, dagger):
+    o, lat, psi = biggest
+    sites = _sample(o)
+    got = _apply(lat, psi, qxd.F64, int(dagger), sites)
+    want = o.schur_sites(psi, sites, dagger=dagger)
+    err = float(np.abs(got - want).max() / np.abs(want).max())
+    print("max-size FP64 D_hat sampled rel err %.2e over %d sites" % (err, sites.size))
+    assert err < 1e-13
+
+
+def test_schur_f32_max_size_sampled(biggest):
+    o, lat, psi = biggest
+    sites = _sample(o, seed=1)
+    got = _apply(lat, psi, qxd.F32, 0, sites)
+    want = o.schur_sites(psi, sites)
+    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    print("max-size FP32 D_hat sampled rel err %.2e" % err)
+    assert err < 1e-6
