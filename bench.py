@@ -93,8 +93,8 @@ def main():
     ap.add_argument("--legs", default="", help="comma-separated solve legs to run (default: all)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the multi-GPU path (time-slab halo exchange over xGMI) "
-              "is a design, not part of this build; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on one GPU (a multi-GPU path with time-slab "
+              "halo exchange over xGMI is designed, not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
