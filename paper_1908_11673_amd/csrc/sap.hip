@@ -90,7 +90,7 @@ __device__ __forceinline__ void sap_face(const Geo& g, const SapGeo& sb, int x0,
     geo_step<MU, +1>(g, x0, x1, x2, x3, neg);
     const int bs = sap_bsite<EO>(sb, x0, x1, x2, x3);
     sp_load(sap_blk<6>(Xb, bs >> 8), kSapSites, bs & 255, s);
-    hop_term<MU, true>(acc, s, u, neg);
+    sap_hop_term<MU, true>(acc, s, u, neg);
   } else if (l == 0) {
     geo_step<MU, -1>(g, x0, x1, x2, x3, neg);
     const int bs = sap_bsite<EO>(sb, x0, x1, x2, x3);
@@ -102,7 +102,7 @@ __device__ __forceinline__ void sap_face(const Geo& g, const SapGeo& sb, int x0,
       float2 w = vb[k * kSapSites];
       v[k] = mk(w.x, w.y);
     }
-    hop_term<MU, false>(acc, s, v, neg);
+    sap_hop_term<MU, false>(acc, s, v, neg);
   }
 }
 
@@ -111,10 +111,12 @@ __device__ __forceinline__ cx<float> sap_alpha(SapLds& L, int t, const cx<float>
   float are = 0.f, aim = 0.f, nn = 0.f;
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    cx<float> vr = cmul_conj(v[c], rho[c]);  // conj(v) rho
-    are += vr.re;
-    aim += vr.im;
-    nn += norm2(v[c]);
+    are = fmaf(v[c].re, rho[c].re, are);  // conj(v) rho
+    are = fmaf(v[c].im, rho[c].im, are);
+    aim = fmaf(v[c].re, rho[c].im, aim);
+    aim = fmaf(-v[c].im, rho[c].re, aim);
+    nn = fmaf(v[c].re, v[c].re, nn);
+    nn = fmaf(v[c].im, v[c].im, nn);
   }
   are = sap_wave_sum(are);
   aim = sap_wave_sum(aim);
@@ -248,8 +250,8 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
       const cx<float> alpha = sap_alpha(L, t, v, rho);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        e[c] = e[c] + alpha * rho[c];
-        rho[c] = rho[c] - alpha * v[c];
+        sap_cmac(e[c], alpha, rho[c]);
+        sap_cmac(rho[c], -alpha, v[c]);
       }
     }
   } else {
@@ -300,8 +302,8 @@ __global__ __launch_bounds__(kSapSites, 2) void k_sap_half(Geo g, SapGeo sb, int
       if (q == 0) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-          e[c] = e[c] + alpha * rho[c];
-          rho[c] = rho[c] - alpha * v[c];
+          sap_cmac(e[c], alpha, rho[c]);
+          sap_cmac(rho[c], -alpha, v[c]);
         }
       }
     }
