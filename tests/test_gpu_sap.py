@@ -98,11 +98,13 @@ def test_sap_fgcr_solves_to_1e10(pair, inner, sap_plain):
     assert res <= 1e-10
 
 
-def test_sap_block_solves_at_64x32x32x32_leave_the_last_colour_nearly_solved():
+@pytest.mark.parametrize("eo", [0, 1], ids=["plain", "evenodd"])
+def test_sap_block_solves_at_64x32x32x32_leave_the_last_colour_nearly_solved(eo):
     """At the benchmark size, in the benchmark's launch configuration: after one
-    cycle whose block solves are nearly exact (40 steps), the residual
-    eta - D x on the blocks visited last is far below the residual on the
-    blocks visited first (a property of the cycle that holds at any size)."""
+    cycle whose block solves are nearly exact (40 steps, plain or the paper's
+    even-odd block solver), the residual eta - D x on the blocks visited last is
+    far below the residual on the blocks visited first (a property of the cycle
+    that holds at any size)."""
     w = sg.WORKLOADS["c1"]
     vp = int(np.prod(w["L"]))
     lat = qxd.Lattice(w["L"], w["cstar"])
@@ -110,7 +112,7 @@ def test_sap_block_solves_at_64x32x32x32_leave_the_last_colour_nearly_solved():
     gen = torch.Generator(device="cuda").manual_seed(11)
     eta = torch.randn(24 * lat.Ve, dtype=torch.complex64, device="cuda", generator=gen)
     x = lat.field(qxd.F32, full=True)
-    qxd.qxd_sap_apply_full(lat.h, 1, 40, 0, x, eta)
+    qxd.qxd_sap_apply_full(lat.h, 1, 40, eo, x, eta)
     dx = lat.field(qxd.F32, full=True)
     qxd.qxd_dw_apply(lat.h, qxd.F32, dx, x)
     r = (eta - dx).cpu().numpy()
@@ -126,5 +128,5 @@ def test_sap_block_solves_at_64x32x32x32_leave_the_last_colour_nearly_solved():
     col = np.stack([colour[par == 0], colour[par == 1]])
     last = np.sqrt(sum(np.sum(np.abs(res[p][:, col[p] == 1]) ** 2) for p in range(2)))
     first = np.sqrt(sum(np.sum(np.abs(res[p][:, col[p] == 0]) ** 2) for p in range(2)))
-    print("residual on the colour solved last %.3e, first %.3e" % (last, first))
+    print("eo %d: residual on the colour solved last %.3e, first %.3e" % (eo, last, first))
     assert last < 1e-3 * first
