@@ -176,16 +176,20 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_mupdate(VT* __restrict__ v, Ptrs 
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// v *= 1/sqrt(scal[i_n2]); partial (v, r)
+// v *= 1/sqrt(scal[i_n2]); partial (v, r).  A norm that is zero or not finite
+// (a Krylov breakdown, e.g. on a vanishing source) sets v = 0 instead, so that
+// the update that follows leaves the residual unchanged.
 template <class VT>
 __global__ __launch_bounds__(QXD_BLOCK) void k_scale_cdot(VT* __restrict__ v, const VT* __restrict__ r, size_t n,
                                                           const double* __restrict__ scal, int i_n2,
                                                           double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
-  double sc = 1.0 / sqrt(scal[i_n2]);
+  const double n2 = scal[i_n2];
+  const bool ok = n2 > 0.0 && n2 < INFINITY;
+  const double sc = ok ? 1.0 / sqrt(n2) : 0.0;
   double re = 0.0, im = 0.0;
   GRID_STRIDE(i, n) {
-    VT vi = wscale(ld_stream(&v[i]), sc);
+    VT vi = ok ? wscale(ld_stream(&v[i]), sc) : VT{};
     st_stream(&v[i], vi);
     wcdot(vi, ld_stream(&r[i]), re, im);
   }

@@ -107,6 +107,21 @@ def test_preconditioner_matches_the_oracle(setup, nc, eo):
     assert err < 1e-4
 
 
+def test_preconditioners_map_zero_to_zero(setup):
+    """The degenerate input: SAP and the deflated preconditioner of a vanishing
+    residual are exactly zero (the coarse GCR meets a zero norm at its first
+    step and must not divide by it)."""
+    o, lat, d, *_ = setup
+    zero = lat.field(qxd.F32)
+    for eo in (0, 1):
+        out = torch.ones(12 * lat.Ve, dtype=torch.complex64, device="cuda")
+        qxd.qxd_dfl_apply(lat.h, d, 8, NCY, NMR, eo, out, zero)
+        assert int(torch.count_nonzero(out)) == 0, eo
+        out = torch.ones(12 * lat.Ve, dtype=torch.complex64, device="cuda")
+        qxd.qxd_sap_apply(lat.h, NCY, NMR, eo, out, zero)
+        assert int(torch.count_nonzero(out)) == 0, eo
+
+
 @pytest.mark.parametrize("inner", [qxd.F32, qxd.BF16], ids=["f32", "bf16links"])
 def test_dfl_fgcr_solves_to_1e10(setup, inner):
     o, lat, d, *_ = setup
