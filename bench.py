@@ -213,7 +213,7 @@ def main():
         del ins, outs
         torch.cuda.empty_cache()
         only = tuple(t for t in args.legs.split(",") if t)
-        train = not big and (not only or "fgcr_f32_nn_in_f64" in only)
+        train = not only or "fgcr_f32_nn_in_f64" in only
         result["time_to_solution"] = solve_leg(qxd, torch, lats, w, flavours, args.nn_fields if train else 0,
                                                args.nn_epochs, big, only)
         if not big and (not only or "shifted" in only):
@@ -453,21 +453,32 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, on
             return lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner, check_every=8), x,
                                             bd, check=False)
 
+        # at 128 x 64^3 the 2 nkv FGCR directions must fit beside the operator: nkv 4
+        nkv = 4 if big else 16
+
         def fgcr(inner, network=None, sap_ncy=0, sap_nmr=8, sap_plain=0):
             prm = qxd.solver_params(res=1e-10, inner_prec=inner, sap_ncy=sap_ncy, sap_nmr=sap_nmr,
-                                    sap_plain=sap_plain)
+                                    sap_plain=sap_plain, nkv=nkv)
             return lambda: qxd.qxd_solve_fgcr(lat.h, prm, network, x, bd, check=False)
 
         legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16))]
-        if not big:  # FGCR's 2 nkv direction vectors do not fit beside the 128 x 64^3 operator
-            legs += [("fgcr_f32_in_f64", fgcr(qxd.F32)), ("fgcr_bf16links_in_f64", fgcr(qxd.BF16)),
+        legs.append(("fgcr_f32_in_f64", fgcr(qxd.F32)))
+        if not big:  # the SAP block copies do not fit beside the 128 x 64^3 operator and FGCR's directions
+            legs += [("fgcr_bf16links_in_f64", fgcr(qxd.BF16)),
                      ("fgcr_f32_sap_in_f64", fgcr(qxd.F32, sap_ncy=SAP_NCY, sap_nmr=SAP_NMR, sap_plain=SAP_PLAIN)),
                      ("fgcr_f32_sap_eo55_in_f64", fgcr(qxd.F32, sap_ncy=5, sap_nmr=5, sap_plain=0))]
         if net is not None:
             legs.append(("fgcr_f32_nn_in_f64", fgcr(qxd.F32, net)))
+        trimmed = False
         for tag, fn in legs:
             if only and tag not in only:
                 continue
+            if big and tag.startswith("fgcr"):
+                if not trimmed:  # drop the CG legs' workspaces before FGCR allocates its own
+                    qxd.qxd_trim(lat.h)
+                    torch.cuda.empty_cache()
+                    trimmed = True
+                fn()  # untimed: the first call allocates the 2 nkv directions
             times = []
             for rep in range(1 if big else 3):
                 torch.cuda.synchronize()
@@ -479,6 +490,8 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, on
                         "iterations": st["inner_it"], "outer": st["outer_it"], "schur_applies": st["schur_applies"],
                         "nn_applies": st["nn_applies"], "sap_applies": st["sap_applies"], "fell_back": st["fell_back"],
                         "true_residual": st["true_residual"]}
+            if tag.startswith("fgcr"):
+                res[tag]["nkv"] = nkv
             log("solve %s %s: %.1f ms, %d it, res %.2e, status %d" % (name, tag, np.median(times), st["inner_it"],
                                                                        st["true_residual"], st["status"]))
         if net is not None:
