@@ -1,10 +1,11 @@
 """Maximum size: the largest one-GPU share, 64^3 x 128 physical with C* in
 three directions (extended 128 x 128 x 64 x 64, 67,108,864 sites; the FP64,
-FP32 and bf16 copies of the operator take about 175 GB of the GPU), up-type
-flavour.  The Schur operator in the launch configuration the benchmark times
-at this size (windows of 16 tiles per XCD), checked against the oracle on
-sampled even sites, including the lattice corners where every C* crossing
-happens; FP64 to 1e-13, FP32 to 1e-6."""
+FP32 and bf16 copies of the operator take about 175 GB of the GPU), down-type
+flavour (the up-type one is checked at 64 x 32^3).  The Schur operator in the
+launch configuration the benchmark times at this size (windows of 16 tiles per
+XCD), checked against the oracle on sampled even sites, including the lattice
+corners where every C* crossing happens (FP64 to 1e-13, FP32 to 1e-6); and a
+mixed-precision solve checked by the oracle's residual on sampled sites."""
 import numpy as np
 import pytest
 
@@ -22,7 +23,7 @@ W = sg.WORKLOADS["c4"]
 
 @pytest.fixture(scope="module")
 def biggest():
-    flav = sg.FLAVOURS["u"]
+    flav = sg.FLAVOURS["d"]
     L = W["L"]
     vphys = int(np.prod(L))
     print("generating %s fields" % (L,), flush=True)
@@ -84,3 +85,35 @@ def test_schur_f32_max_size_sampled(biggest):
     err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
     print("max-size FP32 D_hat sampled rel err %.2e" % err)
     assert err < 1e-6
+
+
+def test_mixed_precision_cg_solves_at_max_size(biggest):
+    """Defect-correction CG (FP32 inner, FP64 outer) at the largest share, after
+    qxd_trim drops the gauge copy: the FP64 true residual 1e-10, and the
+    oracle's residual on sampled even and odd sites (including the corners);
+    the iteration limit bounds the run."""
+    o, lat, _ = biggest
+    qxd.qxd_trim(lat.h)
+    torch.cuda.empty_cache()
+    b = sg.spinor(W["source_seed"] + 1, o.V)
+    bd = lat.pack(to_dev(b))
+    x = lat.field(qxd.F64, full=True)
+    print("solving", flush=True)
+    st = qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32, check_every=8, nmx=3000), x, bd)
+    print("max-size defect-correction CG: %d iterations, true residual %.2e" % (st["inner_it"], st["true_residual"]))
+    assert st["status"] == 0 and st["true_residual"] <= 1e-10
+    del bd
+    qxd.qxd_trim(lat.h)  # the solver's workspaces, before the unpacked solution takes their room
+    torch.cuda.empty_cache()
+    odd = np.nonzero(o.parity() == 1)[0]
+    sites = np.concatenate([_sample(o, seed=2), np.random.default_rng(3).choice(odd, 64, replace=False)])
+    xs = lat.unpack(x)
+    del x
+    xh = np.zeros((o.V, 4, 3), dtype=np.complex128)
+    need = np.unique(np.concatenate([sites, o.neighbours()[0][sites].reshape(-1)]))
+    xh[need] = xs[torch.from_numpy(need).cuda()].cpu().numpy()
+    del xs
+    torch.cuda.empty_cache()
+    res = np.linalg.norm(b[sites] - o.dirac_sites(xh, sites)) / np.linalg.norm(b[sites])
+    print("oracle residual on %d sampled sites: %.2e" % (sites.size, res))
+    assert res <= 1e-9
