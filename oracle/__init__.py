@@ -28,8 +28,13 @@ _lib = None
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc: -O2, no FMA contraction, OpenMP; complex
-    products by the textbook formula (-fcx-limited-range: the same values for
-    finite operands, without a library call per product)."""
+    arithmetic by the textbook formulas (-fcx-limited-range).  For products of
+    finite operands that is the value C99's Annex G gives, without a library
+    call per product.  Complex divisions (the pivoting in the 6x6 block
+    solves) lose Annex G's range reduction: a|b|^2 may round differently, which
+    changes results at the level of a few ulp, and would overflow or underflow
+    only for entries beyond about 1e154 or below 1e-154, far outside any field
+    here."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fcx-limited-range", "-fPIC",

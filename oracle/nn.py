@@ -20,12 +20,44 @@ Weights ``W[l]`` have shape (81, cout, cin); tap = 27(d0+1)+9(d1+1)+3(d2+1)+(d3+
 Backward is the chain rule written out layer by layer: the data gradient of
 a convolution is its adjoint (the oracle's literal scatter), the weight
 gradient is the site sum of (output gradient) x (shifted input).
+
+Storage precision (``bf16=True``).  The network's specification keeps FP32
+master weights and bfloat16 activations.  With ``bf16=True`` every quantity
+that such an implementation stores between layers is rounded to bfloat16
+(binary32 rounded to nearest even, then its upper 16 bits rounded to nearest
+even): the weights, the embedded input, the two ReLU outputs, the gradient at
+the network output and the two masked data gradients; the arithmetic between
+those points stays FP64, and the network output and the weight gradients are
+not rounded.  This is the reference for a bfloat16-storage implementation;
+``bf16=False`` is the exact network.  This module is test infrastructure.
 """
 from __future__ import annotations
 
 import numpy as np
 
 CHANNELS = (24, 32, 32, 24)
+
+
+def bf16_round(a):
+    """Nearest bfloat16 value of each entry, returned as float64.
+
+    bfloat16 keeps the sign, the 8 exponent bits and the top 7 fraction bits
+    of binary32.  The value is first rounded to binary32 (numpy's cast, to
+    nearest even), then the low 16 bits of its encoding are rounded off to
+    nearest, ties to the even upper half.  Finite inputs only."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    low = u & 0xFFFF
+    up = u >> 16
+    up = up + ((low > 0x8000) | ((low == 0x8000) & ((up & 1) == 1)))
+    return (up << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _r(x, bf16):
+    return bf16_round(x) if bf16 else x
+
+
+def _rw(W, bf16):
+    return [bf16_round(w) for w in W] if bf16 else W
 
 
 def embed(o, r):
@@ -45,13 +77,14 @@ def unembed(o, y):
     return out
 
 
-def forward(o, W, r, skip=0.0):
+def forward(o, W, r, skip=0.0, bf16=False):
     """N(r) + skip r and the activations needed by the backward pass."""
-    h0 = embed(o, r)
+    W = _rw(W, bf16)
+    h0 = _r(embed(o, r), bf16)
     a1 = o.nn_conv(W[0], h0)
-    h1 = np.maximum(a1, 0.0)
+    h1 = _r(np.maximum(a1, 0.0), bf16)
     a2 = o.nn_conv(W[1], h1)
-    h2 = np.maximum(a2, 0.0)
+    h2 = _r(np.maximum(a2, 0.0), bf16)
     a3 = o.nn_conv(W[2], h2)
     y = unembed(o, a3)
     if skip:
@@ -59,26 +92,29 @@ def forward(o, W, r, skip=0.0):
     return y, (h0, a1, h1, a2, h2, a3)
 
 
-def apply_precond(o, W, r, skip=0.0):
+def apply_precond(o, W, r, skip=0.0, bf16=False):
     """M(r) = |r| (N(r/|r|) + skip r/|r|)."""
     n = np.linalg.norm(r)
-    y, _ = forward(o, W, r / n, skip)
+    y, _ = forward(o, W, r / n, skip, bf16)
     return n * y
 
 
-def backward(o, W, acts, gy):
-    """Weight gradients given dL/dy (an even-site spinor)."""
+def backward(o, W, acts, gy, bf16=False):
+    """Weight gradients given dL/dy (an even-site spinor).  The ReLU masks are
+    taken where the stored activations are positive (a2 > 0 exactly when the
+    rounded ReLU output h2 is)."""
+    W = _rw(W, bf16)
     h0, a1, h1, a2, h2, a3 = acts
-    g3 = embed(o, gy)
+    g3 = _r(embed(o, gy), bf16)
     dW3 = o.nn_conv_wgrad(g3, h2, 32, 24)
-    g2 = o.nn_conv_adjoint(W[2], g3) * (a2 > 0)
+    g2 = _r(o.nn_conv_adjoint(W[2], g3) * (h2 > 0), bf16)
     dW2 = o.nn_conv_wgrad(g2, h1, 32, 32)
-    g1 = o.nn_conv_adjoint(W[1], g2) * (a1 > 0)
+    g1 = _r(o.nn_conv_adjoint(W[1], g2) * (h1 > 0), bf16)
     dW1 = o.nn_conv_wgrad(g1, h0, 24, 32)
     return [dW1, dW2, dW3]
 
 
-def loss_and_grad(o, W, rs, es, kind=0, skip=0.0):
+def loss_and_grad(o, W, rs, es, kind=0, skip=0.0, bf16=False):
     """Batch loss and its weight gradients; ``rs``, ``es`` are lists of spinors."""
     B = len(rs)
     L = 0.0
@@ -86,7 +122,7 @@ def loss_and_grad(o, W, rs, es, kind=0, skip=0.0):
     for r, e in zip(rs, es):
         n = np.linalg.norm(r)
         rh, eh = r / n, e / n
-        y, acts = forward(o, W, rh, skip)
+        y, acts = forward(o, W, rh, skip, bf16)
         d = y - eh
         if kind == 0:
             ne2 = np.vdot(eh, eh).real
@@ -97,7 +133,7 @@ def loss_and_grad(o, W, rs, es, kind=0, skip=0.0):
             nr2 = np.vdot(rh, rh).real
             L += np.vdot(v, v).real / nr2 / B
             gy = 2.0 * o.schur(v, dagger=True) / nr2 / B
-        for k, g in enumerate(backward(o, W, acts, gy)):
+        for k, g in enumerate(backward(o, W, acts, gy, bf16)):
             grads[k] += g
     return L, grads
 
@@ -114,7 +150,7 @@ def _patch_conv(Wl, h):
     return out
 
 
-def forward_sites(o, W, r, sites, skip=0.0, nb=None):
+def forward_sites(o, W, r, sites, skip=0.0, nb=None, bf16=False):
     """N(r) + skip r at the given sites only, as an (n, 4, 3) array.
 
     The three layers reach three sites in every direction, so each output
@@ -123,7 +159,9 @@ def forward_sites(o, W, r, sites, skip=0.0, nb=None):
     the patch, the site at offset a + d is the tap offset d of the site at
     offset a, because unit steps commute (a C* crossing moves x1 by L1 in
     whichever order the steps are taken).  ``nb``: the neighbour table
-    ``o.neighbours()[0]``, if the caller already has it."""
+    ``o.neighbours()[0]``, if the caller already has it.  ``bf16`` rounds as
+    ``forward`` does."""
+    W = _rw(W, bf16)
     if nb is None:
         nb, _ = o.neighbours()
     par = o.parity()
@@ -144,8 +182,9 @@ def forward_sites(o, W, r, sites, skip=0.0, nb=None):
         h0[..., 0::2] = rr[P].real
         h0[..., 1::2] = rr[P].imag
         h0[par[P] == 1] = 0.0
-        h1 = np.maximum(_patch_conv(W[0], h0), 0.0)
-        h2 = np.maximum(_patch_conv(W[1], h1), 0.0)
+        h0 = _r(h0, bf16)
+        h1 = _r(np.maximum(_patch_conv(W[0], h0), 0.0), bf16)
+        h2 = _r(np.maximum(_patch_conv(W[1], h1), 0.0), bf16)
         y = _patch_conv(W[2], h2)[0, 0, 0, 0]
         out[i] = (y[0::2] + 1j * y[1::2]).reshape(4, 3) + skip * rr[s].reshape(4, 3)
     return out

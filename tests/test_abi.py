@@ -25,6 +25,7 @@ def test_header_declares_the_hot_path_calls():
 
 def test_library_exports_every_declared_symbol():
     import paper_1908_11673_amd as qxd
+    qxd.load()  # builds the library when it is absent (fresh checkout)
     lib = ctypes.CDLL(qxd.lib_path())
     missing = [n for n in declared_entry_points() if not hasattr(lib, n)]
     assert not missing, missing

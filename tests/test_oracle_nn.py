@@ -108,3 +108,112 @@ def test_site_local_forward_equals_the_whole_lattice_forward(L, cstar):
     sites = np.arange(o.V) if o.V <= 1024 else np.random.default_rng(1).choice(o.V, 300, replace=False)
     ys = nn.forward_sites(o, W, r, sites, skip=0.3)
     assert np.abs(ys - y[sites]).max() <= 1e-13 * np.abs(y).max()
+
+
+# ---------------------------------------------------------------------------
+# bfloat16 storage mode: rounding points pinned against torch's own
+# float32 -> bfloat16 conversion (round to nearest even), closed forms with
+# centre-tap weights, and the distance to the exact network.
+
+def _torch_bf16(a):
+    torch = pytest.importorskip("torch")
+    return torch.from_numpy(np.asarray(a, dtype=np.float64)).float().bfloat16().double().numpy()
+
+
+def test_bf16_round_matches_torch_and_ties_to_even():
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.standard_normal(200000) * 10.0 ** rng.integers(-30, 30, 200000),
+                        # exact ties of the low 16 bits, both parities of the kept half
+                        (np.arange(1, 5000, dtype=np.uint32) << 16 | 0x8000).view(np.float32).astype(np.float64),
+                        -(np.arange(1, 5000, dtype=np.uint32) << 16 | 0x8000).view(np.float32).astype(np.float64),
+                        [0.0, -0.0, 1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 3.0e38, -1.0e-39]])
+    got = nn.bf16_round(x)
+    assert np.array_equal(got, _torch_bf16(x))
+    assert nn.bf16_round(np.array([1.0 + 2.0 ** -8]))[0] == 1.0           # tie, even neighbour below
+    assert nn.bf16_round(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6  # tie, even neighbour above
+    assert np.array_equal(nn.bf16_round(got), got)
+
+
+def _centre_weights(c):
+    """Weights whose only nonzero tap is d = 0: c[0] [I 0]^T, c[1] I, c[2] [I 0]."""
+    W = [np.zeros((81, co, ci)) for ci, co in zip(nn.CHANNELS[:-1], nn.CHANNELS[1:])]
+    W[0][40, :24, :] = c[0] * np.eye(24)
+    W[1][40] = c[1] * np.eye(32)
+    W[2][40, :, :24] = c[2] * np.eye(24)
+    return W
+
+
+def test_bf16_forward_closed_form_with_centre_tap_weights():
+    """With centre-tap diagonal weights every layer acts site by site, so the
+    rounded network is y = c2 R(max(c1 R(max(c0 R(r), 0)), 0), 0) on each real
+    channel (R = bfloat16 rounding, torch's).  The c's are bfloat16 numbers
+    whose products with bfloat16 values need rounding again, so leaving out or
+    moving any of the three roundings changes the result."""
+    o = lattice((4, 2, 2, 4), 3)
+    c = (1.0 + 2.0 ** -3 + 2.0 ** -6, 1.0 - 2.0 ** -4 - 2.0 ** -7, 0.75 + 2.0 ** -7)
+    assert all(nn.bf16_round(np.array([ci]))[0] == ci for ci in c)
+    r = sg.spinor(31, o.V)
+    r[o.parity() == 1] = 0
+    y, _ = nn.forward(o, _centre_weights(c), r, bf16=True)
+    h = nn.embed(o, r)
+    want_ch = c[2] * _torch_bf16(np.maximum(c[1] * _torch_bf16(np.maximum(c[0] * _torch_bf16(h), 0.0)), 0.0))
+    want = nn.unembed(o, want_ch)
+    assert np.abs(y - want).max() <= 1e-15 * np.abs(want).max()
+    exact, _ = nn.forward(o, _centre_weights(c), r)
+    assert np.abs(exact - want).max() > 1e-4 * np.abs(want).max()
+
+
+def test_bf16_weight_gradients_closed_form_with_centre_tap_weights():
+    """Centre-tap diagonal weights, error loss: the centre-tap weight gradients
+    are site sums of rounded gradients times rounded activations,
+    dW3 = sum_x g3 h2^T, g2 = R(c2 [I 0]^T g3) [h2 > 0], dW2 = sum_x g2 h1^T,
+    g1 = R(c1 g2) [h1 > 0], dW1 = sum_x g1 h0^T, with g3 = R(dL/dy)."""
+    o = lattice((4, 2, 2, 4), 3)
+    c = (1.0 + 2.0 ** -3 + 2.0 ** -6, 1.0 - 2.0 ** -4 - 2.0 ** -7, 0.75 + 2.0 ** -7)
+    W = _centre_weights(c)
+    par = o.parity()
+    r = sg.spinor(32, o.V)
+    e = sg.spinor(33, o.V)
+    r[par == 1] = 0
+    e[par == 1] = 0
+    L, grads = nn.loss_and_grad(o, W, [r], [e], kind=0, bf16=True)
+    n = np.linalg.norm(r)
+    rh, eh = r / n, e / n
+    h0 = _torch_bf16(nn.embed(o, rh))
+    h1 = _torch_bf16(np.maximum(c[0] * np.pad(h0, ((0, 0), (0, 8))), 0.0))
+    h2 = _torch_bf16(np.maximum(c[1] * h1, 0.0))
+    y = nn.unembed(o, c[2] * h2[:, :24])
+    d = y - eh
+    ne2 = np.vdot(eh, eh).real
+    assert abs(L - np.vdot(d, d).real / ne2) <= 1e-13 * L
+    g3 = _torch_bf16(nn.embed(o, 2.0 * d / ne2))
+    g2 = _torch_bf16(c[2] * np.pad(g3, ((0, 0), (0, 8)))) * (h2 > 0)
+    g1 = _torch_bf16(c[1] * g2) * (h1 > 0)
+    want = [g1.T @ h0, g2.T @ h1, g3.T @ h2]
+    for k in range(3):
+        assert np.abs(grads[k][40] - want[k]).max() <= 1e-13 * np.abs(want[k]).max(), k
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_bf16_network_stays_within_bf16_bounds_of_the_exact_one(kind):
+    """Random weights: the rounded network and its gradients differ from the
+    exact ones by bfloat16-sized amounts (rounding on, but no gross change)."""
+    o = lattice()
+    o.set_gauge_physical(sg.gauge_su3(3, 0.3, o.Vphys), sg.gauge_u1(3, 0.3, o.Vphys))
+    o.set_flavour(**sg.FLAVOURS["d"])
+    W = weights(11, scale=1.5)
+    par = o.parity()
+    r = sg.spinor(101, o.V)
+    e = sg.spinor(201, o.V)
+    r[par == 1] = 0
+    e[par == 1] = 0
+    y, _ = nn.forward(o, W, r)
+    yb, _ = nn.forward(o, W, r, bf16=True)
+    dy = np.linalg.norm(yb - y) / np.linalg.norm(y)
+    assert 1e-4 < dy < 2e-2, dy
+    L, g = nn.loss_and_grad(o, W, [r], [e], kind)
+    Lb, gb = nn.loss_and_grad(o, W, [r], [e], kind, bf16=True)
+    assert abs(Lb - L) < 2e-2 * L
+    for k in range(3):
+        dg = np.linalg.norm(gb[k] - g[k]) / np.linalg.norm(g[k])
+        assert 1e-4 < dg < 5e-2, (k, dg)
