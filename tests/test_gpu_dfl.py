@@ -2,7 +2,8 @@
 oracle from the same seeded start vectors: the vectors after SAP inverse
 iteration, the block basis, the little operator (as a dense matrix, blocks
 matched by their coordinates) and the two-level preconditioner; FP32 on the
-GPU, so the bar is 1e-4 relative (measured about 1e-7); then DFL-preconditioned
+GPU, so the bar is 1e-6 relative, about eight FP32 unit roundoffs (measured
+1.2e-7 to 1.8e-7 on both geometries); then DFL-preconditioned
 FGCR solves to the FP64 true residual 1e-10 checked by the oracle's D, the
 subspace-state errors, and a 32x16^3 solve where deflation cuts the FGCR steps."""
 import numpy as np
@@ -60,7 +61,7 @@ def test_inverse_iteration_matches_the_oracle(setup):
         got = lat.unpack(v[k * n:(k + 1) * n], qxd.F32).cpu().numpy()
         err = np.linalg.norm(got - vs[k]) / np.linalg.norm(vs[k])
         print("vector %d: %.2e" % (k, err))
-        assert err < 1e-5
+        assert err < 1e-6
 
 
 def test_block_basis_matches_the_oracle(setup):
@@ -73,7 +74,7 @@ def test_block_basis_matches_the_oracle(setup):
         for s, Q in zip(sites, basis):
             worst = max(worst, np.linalg.norm(w[s].reshape(-1) - Q[k]))
     print("basis: max |w_gpu - w_oracle| %.2e" % worst)
-    assert worst < 1e-4
+    assert worst < 1e-6
 
 
 def test_little_operator_matches_the_oracle(setup):
@@ -89,7 +90,7 @@ def test_little_operator_matches_the_oracle(setup):
             dense[r * NS:(r + 1) * NS, c * NS:(c + 1) * NS] += Ag[R, n].T  # stored [k][l]
     err = np.abs(dense - A).max() / np.abs(A).max()
     print("little operator: %.2e" % err)
-    assert err < 1e-4
+    assert err < 1e-6
 
 
 @pytest.mark.parametrize("nc,eo", [(2, 0), (8, 0), (8, 1)])
@@ -104,7 +105,7 @@ def test_preconditioner_matches_the_oracle(setup, nc, eo):
     want = odfl.precondition_even(o, sites, basis, A, r, nc, NCY, NMR, bool(eo), blocks)
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
     print("nc %d eo %d: %.2e" % (nc, eo, err))
-    assert err < 1e-4
+    assert err < 1e-6
 
 
 def test_preconditioners_map_zero_to_zero(setup):

@@ -99,7 +99,7 @@ def test_sampled_block_bases_are_orthonormal(full):
         Q = Q.reshape(NS, -1)
         worst = max(worst, np.abs(Q.conj() @ Q.T - np.eye(NS)).max())
     print("max |W_B^+ W_B - 1| over %d blocks: %.2e" % (len(basis), worst))
-    assert worst < 1e-5
+    assert worst < 1e-6  # measured 1.2e-7
 
 
 def test_little_operator_rows_on_sampled_blocks(full):
@@ -127,7 +127,7 @@ def test_little_operator_rows_on_sampled_blocks(full):
         reach = {gpu_block(o, o.coords(s)) for s in nb_sites[sites[C]].reshape(-1)} | {C}
         assert reach == set(touched), (C, sorted(reach), sorted(touched))
     print("little operator: max |A_gpu - (w, D w)| / max |A| = %.2e" % (worst / scale))
-    assert worst < 1e-4 * scale
+    assert worst < 1e-6 * scale  # measured 9.6e-8
 
 
 def test_deflated_solve_reaches_1e10(full):

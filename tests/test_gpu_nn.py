@@ -1,11 +1,17 @@
 """Learned preconditioner on the GPU, through the C ABI.
 
-Forward and weight gradients are compared with the FP64 network oracle run on
-the same weights rounded to bfloat16 (the GPU contracts bf16 operands on the
-matrix cores and stores bf16 activations, so a few 1e-3 of relative noise per
-layer remain: the bars are 2e-2 for outputs and losses, 6e-2 for gradients, in
-norm).  Training, the preconditioned solve and the fallbacks are checked on the
-FP64 true residual."""
+Forward and weight gradients are compared with the network oracle in its
+bfloat16 storage mode, which rounds the weights, the embedded input, the ReLU
+outputs and the back-propagated gradients to bfloat16 where the kernels store
+them, on the FP32-rounded input the GPU receives.  What remains is FP32
+accumulation on the matrix cores against FP64 in the oracle, and the rare
+bfloat16 rounding it flips.  Bars, in norm: every layer's weight gradient
+1e-2, the network's tolerance for bfloat16 storage (measured at most 1.9e-3,
+layer 1); the output 2e-3 (measured at most 1.8e-4); the loss 1e-4 (measured
+at most 1.4e-6).  The distance to the exact FP64 network (4e-3 for outputs, up
+to 5.7e-2 for gradients) is printed beside it.  Training, the
+preconditioned solve and the fallbacks are checked on the FP64 true
+residual."""
 import os
 
 import numpy as np
@@ -36,10 +42,9 @@ def flat(ws):
     return np.concatenate([w.reshape(-1) for w in ws]).astype(np.float32)
 
 
-def bf16_round(a):
-    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+def f32(a):
+    """the FP32 rounding the GPU's input fields receive"""
+    return np.asarray(a).astype(np.complex64).astype(np.complex128)
 
 
 def half32(lat, o, psi):
@@ -93,10 +98,12 @@ def test_forward_matches_oracle(lat_pair, skip):
     out = lat.field(qxd.F32)
     qxd.qxd_nn_apply(lat.h, net, out, half32(lat, o, r))
     got = from_half32(lat, o, out)
-    want = onn.apply_precond(o, [bf16_round(w) for w in ws], r, skip)
+    want = onn.apply_precond(o, ws, f32(r), skip, bf16=True)
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
-    print("nn forward rel err %.2e" % err)
-    assert err < 2e-2
+    exact = onn.apply_precond(o, ws, r, skip)
+    print("nn forward rel err %.2e (exact FP64 network: %.2e)" % (
+        err, np.linalg.norm(got - exact) / np.linalg.norm(exact)))
+    assert err < 2e-3
     assert np.abs(got[o.parity() == 1]).max() == 0
     # positive homogeneity: M(2 r) = 2 M(r) exactly
     out2 = lat.field(qxd.F32)
@@ -125,18 +132,19 @@ def test_loss_and_gradient_match_oracle(lat_pair, kind, skip):
     R = torch.cat([half32(lat, o, r) for r in rs])
     E = torch.cat([half32(lat, o, e) for e in es])
     loss, grad = qxd.qxd_nn_loss_grad(lat.h, net, R, E, 2, kind)
-    wr = [bf16_round(w) for w in ws]
-    L0, g0 = onn.loss_and_grad(o, wr, rs, es, kind, skip)
-    print("loss gpu %.6f oracle %.6f" % (loss, L0))
-    assert abs(loss - L0) / L0 < 2e-2
+    L0, g0 = onn.loss_and_grad(o, ws, [f32(r) for r in rs], [f32(e) for e in es], kind, skip, bf16=True)
+    Lx, gx = onn.loss_and_grad(o, ws, rs, es, kind, skip)
+    print("loss gpu %.6f oracle %.6f (exact %.6f)" % (loss, L0, Lx))
+    assert abs(loss - L0) / L0 < 1e-4
     off = 0
     for k, (ci, co) in enumerate(SHAPES):
         n = 81 * co * ci
         gk = grad[off:off + n].reshape(81, co, ci)
         off += n
         err = np.linalg.norm(gk - g0[k]) / np.linalg.norm(g0[k])
-        print("layer %d grad rel err %.2e" % (k + 1, err))
-        assert err < 6e-2
+        print("layer %d grad rel err %.2e (exact FP64 network: %.2e)" % (
+            k + 1, err, np.linalg.norm(gk - gx[k]) / np.linalg.norm(gx[k])))
+        assert err < 1e-2
     qxd.qxd_nn_destroy(net)
 
 

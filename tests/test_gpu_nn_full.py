@@ -2,9 +2,11 @@
 64 physical lattice with C* in three directions (extended 64 x 64 x 32 x 32),
 the launch the benchmark's network-preconditioned solve makes (block-tiled
 convolution, persistent workgroups walking 8,192 blocks of 4 x 4 x 4 x 8),
-checked on sampled even sites against the FP64 network oracle evaluated site by
-site on the same weights rounded to bfloat16 (the bar of the small-lattice
-tests, 2e-2 in norm, for the bf16 operands and activations)."""
+checked on sampled even sites against the network oracle evaluated site by
+site in its bfloat16 storage mode (weights, input and ReLU outputs rounded
+where the kernels store them) on the FP32-rounded input: 2e-3 in norm, the
+bar of the small-lattice tests (measured 1.6e-4), and 5e-3 for the worst
+single site against the rms output (measured 7.2e-4)."""
 import numpy as np
 import pytest
 
@@ -25,12 +27,6 @@ SHAPES = [(24, 32), (32, 32), (32, 24)]
 def init_weights(seed):
     return [sg.gaussian(seed, k, np.sqrt(2.0 / (81 * ci)), 81 * co * ci).reshape(81, co, ci)
             for k, (ci, co) in enumerate(SHAPES)]
-
-
-def bf16_round(a):
-    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 @pytest.fixture(scope="module")
@@ -69,12 +65,13 @@ def test_network_apply_full_size_sampled(full, skip):
     full_out[:12 * lat.Ve] = out
     got = lat.unpack(full_out, qxd.F32)[torch.from_numpy(sites).cuda()].cpu().numpy()
     qxd.qxd_nn_destroy(net)
-    n = np.linalg.norm(r)
-    want = n * onn.forward_sites(o, [bf16_round(w) for w in ws], r / n, sites, skip, nb=nb)
+    r32 = r.astype(np.complex64).astype(np.complex128)
+    n = np.linalg.norm(r32)
+    want = n * onn.forward_sites(o, ws, r32 / n, sites, skip, nb=nb, bf16=True)
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
     # no single site far off either, measured against the sampled sites' rms output
     rms = np.linalg.norm(want) / np.sqrt(len(sites))
     worst = np.linalg.norm((got - want).reshape(len(sites), -1), axis=1).max() / rms
     print("skip %.2f: %d sampled sites, rel err %.2e, worst site %.2e of the rms" % (skip, len(sites), err, worst))
-    assert err < 2e-2
-    assert worst < 5e-2
+    assert err < 2e-3
+    assert worst < 5e-3
