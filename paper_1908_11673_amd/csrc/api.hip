@@ -58,7 +58,6 @@ extern "C" qxd_status qxd_create(const qxd_geom* g, qxd_handle** out) {
     h->geo.tchunk = std::atoi(e);
     h->tchunk_env = true;
   }
-  if (const char* e = std::getenv("QXD_STREAM_KERNELS")) h->stream_kernels = std::atoi(e) != 0;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return QXD_EHIP;

@@ -73,133 +73,6 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_schur2(Geo g, const SPT* __restri
   }
 }
 
-// ---------------------------------------------------------------------------
-// Time-streaming variants of the two Schur passes.  A workgroup owns a tile of
-// NTH consecutive half sites of a time slice (slice = S = Le1 Le2 Le3/2 half
-// sites) and walks TT consecutive slices.  The input field of the tile is kept in
-// an LDS ring of three slices (t-1, t, t+1): the hops along t read the same tile
-// position one slice up or down (same x3, so the same half-index offset), and
-// the spatial hops that stay inside the tile read the current slice, all from
-// LDS; only hops leaving the tile (x1, and the x2 tile edges) go to memory.
-// Every input spinor is thus read from memory about (1 + 2/TT) times instead
-// of being fetched again for each of its time neighbours.
-
-#define QXD_TNTH 128
-
-template <class T>
-__device__ __forceinline__ void ring_store(cx<T> (*ring)[QXD_TNTH], int slot, int i, const cx<T> v[12]) {
-#pragma unroll
-  for (int c = 0; c < 12; ++c) ring[slot * 12 + c][i] = v[c];
-}
-template <class T>
-__device__ __forceinline__ void ring_load(cx<T> (*ring)[QXD_TNTH], int slot, int i, cx<T> v[12]) {
-#pragma unroll
-  for (int c = 0; c < 12; ++c) v[c] = ring[slot * 12 + c][i];
-}
-
-// spatial hops (MU = 1..3) of the site at coordinates x in slice t
-template <int MU, bool G5IN, class T, class SPT, class LKT>
-__device__ __forceinline__ void hop_mu_tile(const Geo& g, int h, int x0, int x1, int x2, int x3, int tS, int j0,
-                                            const SPT* __restrict__ in, const LKT* __restrict__ Vp,
-                                            const LKT* __restrict__ Vq, cx<T> (*ring)[QXD_TNTH], int scur,
-                                            cx<T> acc[12]) {
-  const size_t Ve = g.Ve;
-  bool neg;
-  cx<T> s[12], u[9];
-  int hf = geo_nb<MU, +1>(g, x0, x1, x2, x3, neg);
-  int of = hf - tS - j0;
-  if ((unsigned)of < (unsigned)QXD_TNTH) ring_load(ring, scur, of, s);
-  else sp_load(in, Ve, hf, s);
-  if (G5IN) g5_lower(s);
-  lk_load(Vp, Ve, MU, h, u);
-  hop_term<MU, true>(acc, s, u, false);
-  __builtin_amdgcn_sched_barrier(0);
-  int hb = geo_nb<MU, -1>(g, x0, x1, x2, x3, neg);
-  int ob = hb - tS - j0;
-  if ((unsigned)ob < (unsigned)QXD_TNTH) ring_load(ring, scur, ob, s);
-  else sp_load(in, Ve, hb, s);
-  if (G5IN) g5_lower(s);
-  lk_load(Vq, Ve, MU, hb, u);
-  hop_term<MU, false>(acc, s, u, false);
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-// PASS 1: p = 1 (odd outputs), out = Hc acc, input g5 when DAG.
-// PASS 2: p = 0 (even outputs), out = Hc psi - (1/4) g5^DAG acc, optional |out|^2 partials.
-template <int PASS, class T, class SPT, class LKT, class CLT, bool DAG, bool NORM, int TT>
-__global__ __launch_bounds__(QXD_TNTH) void k_schur_t(Geo g, int S, const SPT* __restrict__ in,
-                                                      const SPT* __restrict__ psi_e, SPT* __restrict__ out,
-                                                      const LKT* __restrict__ Vp, const LKT* __restrict__ Vq,
-                                                      const CLT* __restrict__ Hc, double* __restrict__ partial) {
-  __shared__ cx<T> ring[3 * 12][QXD_TNTH];
-  __shared__ double sh[QXD_TNTH / 64];
-  constexpr bool G5IN = (PASS == 1) && DAG;
-  const int p = PASS == 1 ? 1 : 0;
-  const int ntile = S / QXD_TNTH;
-  const int logical = site_tile(blockIdx.x, gridDim.x, g.tchunk);
-  const int jt = logical % ntile, tc = logical / ntile;
-  const int j0 = jt * QXD_TNTH, tid = threadIdx.x, off = j0 + tid;
-  const int t0 = tc * TT;
-  const size_t Ve = g.Ve;
-  cx<T> v[12];
-  {
-    int tm = t0 == 0 ? g.Le0 - 1 : t0 - 1;
-    sp_load(in, Ve, tm * S + off, v);
-    ring_store(ring, (t0 + 2) % 3, tid, v);  // slot of t0 - 1
-    sp_load(in, Ve, t0 * S + off, v);
-    ring_store(ring, t0 % 3, tid, v);
-  }
-  double n2 = 0.0;
-#pragma unroll 1
-  for (int t = t0; t < t0 + TT; ++t) {
-    const int tp = t + 1 == g.Le0 ? 0 : t + 1;
-    sp_load(in, Ve, tp * S + off, v);
-    ring_store(ring, (t + 1) % 3, tid, v);
-    __syncthreads();
-    const int sprev = (t + 2) % 3, scur = t % 3, snext = (t + 1) % 3;
-    const int h = t * S + off;
-    int x0, x1, x2, x3;
-    geo_decode(g, p, h, x0, x1, x2, x3);
-    cx<T> acc[12], s[12], u[9];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = mk(T(0), T(0));
-    // time direction from the ring
-    ring_load(ring, snext, tid, s);
-    if (G5IN) g5_lower(s);
-    lk_load(Vp, Ve, 0, h, u);
-    hop_term<0, true>(acc, s, u, g.tanti && t == g.Le0 - 1);
-    __builtin_amdgcn_sched_barrier(0);
-    const int tm = t == 0 ? g.Le0 - 1 : t - 1;
-    ring_load(ring, sprev, tid, s);
-    if (G5IN) g5_lower(s);
-    lk_load(Vq, Ve, 0, tm * S + off, u);
-    hop_term<0, false>(acc, s, u, g.tanti && t == 0);
-    __builtin_amdgcn_sched_barrier(0);
-    const int tS = t * S;
-    hop_mu_tile<1, G5IN, T>(g, h, x0, x1, x2, x3, tS, j0, in, Vp, Vq, ring, scur, acc);
-    hop_mu_tile<2, G5IN, T>(g, h, x0, x1, x2, x3, tS, j0, in, Vp, Vq, ring, scur, acc);
-    hop_mu_tile<3, G5IN, T>(g, h, x0, x1, x2, x3, tS, j0, in, Vp, Vq, ring, scur, acc);
-    cx<T> o[12];
-    if (PASS == 1) {
-      clover_mul<T>(Hc, Ve, h, acc, o);
-    } else {
-      if (DAG) g5_lower(acc);
-      cx<T> ps[12];
-      sp_load(psi_e, Ve, h, ps);
-      clover_mul<T>(Hc, Ve, h, ps, o);
-#pragma unroll
-      for (int k = 0; k < 12; ++k) o[k] = o[k] - T(0.25) * acc[k];
-      if (NORM) n2 += sp_norm2(o);
-    }
-    sp_store(out, Ve, h, o);
-    __syncthreads();
-  }
-  if (NORM) {
-    double b = block_sum(n2, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = b;
-  }
-}
-
 // full operator on parity p: out_p = H_p in_p - (1/2) hop(in_q)
 template <class T, class SPT, class LKT, class CLT>
 __global__ __launch_bounds__(QXD_BLOCK) void k_dw(Geo g, int p, const SPT* __restrict__ in_p,
@@ -297,53 +170,12 @@ static qxd_status ensure_t(qxd_handle* h, qxd_prec p) {
 }
 
 
-// time steps per workgroup of the streaming kernels (0: use the per-site kernels)
-static int stream_steps(const qxd_handle* h) {
-  int S = (int)(h->Ve / h->geo.Le0);
-  if (S % QXD_TNTH != 0 || h->Ve < 8192) return 0;
-  for (int tt : {8, 4, 2})
-    if (h->geo.Le0 % tt == 0) return tt;
-  return 0;
-}
-
-template <int PASS, class T, class SPT, class LKT, class CLT, bool DAG, bool NORM>
-static void launch_t(qxd_handle* h, int tt, const SPT* in, const SPT* psi, SPT* out, const LKT* Vp, const LKT* Vq,
-                     const CLT* Hc, hipStream_t s) {
-  int S = (int)(h->Ve / h->geo.Le0);
-  int G = (S / QXD_TNTH) * (h->geo.Le0 / tt);
-  if (tt == 8)
-    hipLaunchKernelGGL((k_schur_t<PASS, T, SPT, LKT, CLT, DAG, NORM, 8>), dim3(G), dim3(QXD_TNTH), 0, s, h->geo, S, in,
-                       psi, out, Vp, Vq, Hc, h->partial);
-  else if (tt == 4)
-    hipLaunchKernelGGL((k_schur_t<PASS, T, SPT, LKT, CLT, DAG, NORM, 4>), dim3(G), dim3(QXD_TNTH), 0, s, h->geo, S, in,
-                       psi, out, Vp, Vq, Hc, h->partial);
-  else
-    hipLaunchKernelGGL((k_schur_t<PASS, T, SPT, LKT, CLT, DAG, NORM, 2>), dim3(G), dim3(QXD_TNTH), 0, s, h->geo, S, in,
-                       psi, out, Vp, Vq, Hc, h->partial);
-}
-
 template <class T, class SPT, class LKT, class CLT>
 static void launch_schur(qxd_handle* h, int dagger, SPT* out, const SPT* in, SPT* t, const LKT* V, const CLT* He,
                          const CLT* Hi, double* norm_slot, hipStream_t s) {
   const size_t lk_half = (size_t)4 * 9 * h->Ve;
   const LKT* Ve_l = V;
   const LKT* Vo_l = V + lk_half;
-  int tt = stream_steps(h);
-  if (tt > 0 && h->stream_kernels) {
-    int S = (int)(h->Ve / h->geo.Le0);
-    int G = (S / QXD_TNTH) * (h->geo.Le0 / tt);
-    if (dagger) {
-      launch_t<1, T, SPT, LKT, CLT, true, false>(h, tt, in, nullptr, t, Vo_l, Ve_l, Hi, s);
-      if (norm_slot) launch_t<2, T, SPT, LKT, CLT, true, true>(h, tt, t, in, out, Ve_l, Vo_l, He, s);
-      else launch_t<2, T, SPT, LKT, CLT, true, false>(h, tt, t, in, out, Ve_l, Vo_l, He, s);
-    } else {
-      launch_t<1, T, SPT, LKT, CLT, false, false>(h, tt, in, nullptr, t, Vo_l, Ve_l, Hi, s);
-      if (norm_slot) launch_t<2, T, SPT, LKT, CLT, false, true>(h, tt, t, in, out, Ve_l, Vo_l, He, s);
-      else launch_t<2, T, SPT, LKT, CLT, false, false>(h, tt, t, in, out, Ve_l, Vo_l, He, s);
-    }
-    if (norm_slot) launch_final_sum(h->partial, G, 1, G, norm_slot, s);
-    return;
-  }
   int G = div_up(h->Ve, QXD_BLOCK);
   if (dagger)
     hipLaunchKernelGGL((k_schur1<T, SPT, LKT, CLT, true>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, in, t, Ve_l, Vo_l, Hi);

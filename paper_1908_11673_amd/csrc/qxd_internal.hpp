@@ -362,7 +362,6 @@ struct qxd_handle {
   double* scal_host = nullptr;  // pinned mirror
   size_t npartial = 0;        // doubles in `partial`
   bool tchunk_env = false;    // walk chunk fixed by QXD_TILE_CHUNK
-  bool stream_kernels = false; // time-streaming Schur kernels (measured slower; kept for tuning)
   uint64_t setup_gen = 0;     // bumped whenever the links or clover blocks are rebuilt
   uint64_t sap_gen = 0;       // SAP's block-order copies: 2 setup_gen + slot order (0: none)
   // solver workspaces (grow-only), indexed by role

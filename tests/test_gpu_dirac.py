@@ -23,7 +23,7 @@ GEOMS = [
     ((6, 2, 6, 4), 3, False),
     ((4, 4, 4, 6), 3, True),
     ((2, 2, 2, 2), 3, False),
-    ((8, 8, 8, 16), 3, False),     # large enough for the time-streaming Schur kernels
+    ((8, 8, 8, 16), 3, False),     # 8192 even sites: 32 workgroups, windows of the XCD-aware walk
     ((8, 8, 8, 16), 2, True),
 ]
 
