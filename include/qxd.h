@@ -66,7 +66,8 @@ typedef enum {
   QXD_ENAN = 5,       /* a non-finite value reached a solver reduction */
   QXD_ENOCONV = 6,    /* the iteration limit was reached before the target */
   QXD_EHIP = 7,       /* a HIP runtime call failed */
-  QXD_ESTATE = 8      /* call out of order (e.g. apply before clover_invert) */
+  QXD_ESTATE = 8,     /* call out of order (e.g. apply before clover_invert) */
+  QXD_ESCRATCH = 9    /* the lattice needs more than the static workspace of a no-allocation call */
 } qxd_status;
 
 typedef enum { QXD_F64 = 0, QXD_F32 = 1, QXD_BF16 = 2 } qxd_prec;
@@ -177,6 +178,23 @@ qxd_status qxd_dw_apply(qxd_handle *h, qxd_prec p, void *out, const void *in, vo
  * (dagger = 1) (Sec. 2.3), even half fields of precision p.  Uses an internal
  * odd half field as workspace.  out_e and in_e must not overlap. */
 qxd_status qxd_dw_eo_schur(qxd_handle *h, qxd_prec p, int dagger, void *out_e, const void *in_e, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * out_e = D_hat in_e / D_hat^+ in_e as qxd_dw_eo_schur, with the same kernels
+ * and bit-identical results, but the odd half field of workspace is taken from
+ * a static device array of QXD_NOALLOC_SCRATCH_BYTES per GPU (held from the
+ * library's first use on a GPU until the process ends) instead of a handle
+ * buffer allocated on first use; the call allocates and frees nothing.
+ * QXD_ESCRATCH when the half field (192 Ve bytes F64, 96 Ve F32, 48 Ve BF16)
+ * exceeds the array: up to Ve = 349,525 in F64, 699,050 in F32, 1,398,101 in
+ * BF16.  QXD_EINVAL when the current device is not the handle's.  All calls on
+ * one GPU share its array, which keeps the last call's contents: calls that
+ * overlap in time on one GPU (several streams or host threads) race; serialise
+ * them.  Nothing in the array needs to start at zero. */
+#define QXD_NOALLOC_SCRATCH_BYTES (64u << 20)
+qxd_status qxd_dw_eo_schur_noalloc(qxd_handle *h, qxd_prec p, int dagger, void *out_e, const void *in_e,
+                                   void *stream);
 
 /* bhat_e = b_e - D_eo D_oo^-1 b_o  (F64; b full field, bhat_e even half field). */
 qxd_status qxd_eo_source(qxd_handle *h, void *bhat_e, const void *b, void *stream);

@@ -25,7 +25,8 @@ PRECOND_NONE, PRECOND_NN = 0, 1
 NN_NWEIGHTS = 207360
 
 STATUS = {0: "QXD_OK", 1: "QXD_EINVAL", 2: "QXD_EGEOM", 3: "QXD_ENOMEM", 4: "QXD_ESINGULAR",
-          5: "QXD_ENAN", 6: "QXD_ENOCONV", 7: "QXD_EHIP", 8: "QXD_ESTATE"}
+          5: "QXD_ENAN", 6: "QXD_ENOCONV", 7: "QXD_EHIP", 8: "QXD_ESTATE",
+          9: "QXD_ESCRATCH"}
 
 
 class QxdError(RuntimeError):
@@ -90,6 +91,7 @@ _SIGNATURES = {
     "qxd_clover_invert": ([_P, ctypes.POINTER(qxd_clover_stats), _P], _I),
     "qxd_dw_apply": ([_P, _I, _P, _P, _P], _I),
     "qxd_dw_eo_schur": ([_P, _I, _I, _P, _P, _P], _I),
+    "qxd_dw_eo_schur_noalloc": ([_P, _I, _I, _P, _P, _P], _I),
     "qxd_eo_source": ([_P, _P, _P, _P], _I),
     "qxd_eo_reconstruct": ([_P, _P, _P, _P, _P], _I),
     "qxd_pack": ([_P, _I, _P, _P, _P], _I),
@@ -233,6 +235,11 @@ def qxd_dw_apply(h, prec, out, inp, stream=None):
 def qxd_dw_eo_schur(h, prec, dagger, out_e, in_e, stream=None):
     _check(load().qxd_dw_eo_schur(h, int(prec), int(bool(dagger)), _ptr(out_e), _ptr(in_e), _stream(stream)),
            "qxd_dw_eo_schur")
+
+
+def qxd_dw_eo_schur_noalloc(h, prec, dagger, out_e, in_e, stream=None):
+    _check(load().qxd_dw_eo_schur_noalloc(h, int(prec), int(bool(dagger)), _ptr(out_e), _ptr(in_e),
+                                          _stream(stream)), "qxd_dw_eo_schur_noalloc")
 
 
 def qxd_eo_source(h, bhat_e, b, stream=None):

@@ -15,6 +15,7 @@ extern "C" const char* qxd_status_string(qxd_status s) {
     case QXD_ENOCONV: return "QXD_ENOCONV";
     case QXD_EHIP: return "QXD_EHIP";
     case QXD_ESTATE: return "QXD_ESTATE";
+    case QXD_ESCRATCH: return "QXD_ESCRATCH";
   }
   return "QXD_UNKNOWN";
 }
@@ -58,7 +59,7 @@ extern "C" qxd_status qxd_create(const qxd_geom* g, qxd_handle** out) {
     h->geo.tchunk = std::atoi(e);
     h->tchunk_env = true;
   }
-  if (hipGetDevice(&h->device) != hipSuccess) {
+  if (hipGetDevice(&h->device) != hipSuccess || scratch_resolve(h->device) != QXD_OK) {
     delete h;
     return QXD_EHIP;
   }

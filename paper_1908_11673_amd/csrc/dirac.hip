@@ -12,6 +12,8 @@
 // One work-item per output site; neighbours are found from the site
 // coordinates (no neighbour table), including the C* shift of x1 when a hop in
 // direction k <= cstar crosses the lattice boundary.
+#include <mutex>
+
 #include "wilson_site.hpp"
 
 __device__ inline double block_sum(double v, double* sh) {
@@ -253,6 +255,68 @@ extern "C" qxd_status qxd_dw_eo_schur(qxd_handle* h, qxd_prec p, int dagger, voi
   if (!h || !out_e || !in_e || out_e == in_e) return QXD_EINVAL;
   if (p != QXD_F64 && p != QXD_F32 && p != QXD_BF16) return QXD_EINVAL;
   return qxd_schur_apply(h, p, dagger ? 1 : 0, out_e, in_e, nullptr, as_stream(stream));
+}
+
+// ---------------------------------------------------------------------------
+// D_hat without allocation.  The odd-site workspace t_o of the two passes lives
+// in a static device array instead of a handle buffer allocated on first use,
+// so the call allocates nothing.  In host code `scratch` names the host-side
+// shadow of the array, not device memory: its device address (one copy per
+// GPU) is looked up once per device by scratch_resolve and only that address
+// is ever handed to a kernel.  Nothing in the array must start at zero (pass 1
+// writes every odd site before pass 2 reads it); calls that overlap on one GPU
+// share the array and race.
+
+static __device__ __align__(256) unsigned char scratch[QXD_NOALLOC_SCRATCH_BYTES];
+
+#define QXD_MAX_DEVICES 64
+static void* g_scratch_dev[QXD_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+qxd_status scratch_resolve(int device) {
+  if (device < 0 || device >= QXD_MAX_DEVICES) return QXD_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return QXD_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return QXD_EHIP;
+  g_scratch_dev[device] = ptr;
+  return QXD_OK;
+}
+
+static void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < QXD_MAX_DEVICES ? g_scratch_dev[device] : nullptr;
+}
+
+extern "C" qxd_status qxd_dw_eo_schur_noalloc(qxd_handle* h, qxd_prec p, int dagger, void* out_e, const void* in_e,
+                                              void* stream) {
+  if (!h || !out_e || !in_e || out_e == in_e) return QXD_EINVAL;
+  if (p != QXD_F64 && p != QXD_F32 && p != QXD_BF16) return QXD_EINVAL;
+  if (!h->has_inverse) return QXD_ESTATE;
+  if (half_bytes(h, p) > (size_t)QXD_NOALLOC_SCRATCH_BYTES) return QXD_ESCRATCH;
+  int dev = -1;
+  QXD_HIP(hipGetDevice(&dev));
+  if (dev != h->device) return QXD_EINVAL;
+  void* t = scratch_of(dev);
+  if (!t) return QXD_ESTATE;  // qxd_create resolves it for the handle's device
+  hipStream_t s = as_stream(stream);
+  h->geo.tchunk = walk_chunk(h, p);
+  switch (p) {
+    case QXD_F64:
+      launch_schur<double>(h, dagger ? 1 : 0, (double2*)out_e, (const double2*)in_e, (double2*)t,
+                           (const double2*)h->V64, (const double2*)h->He64, (const double2*)h->Hi64, nullptr, s);
+      break;
+    case QXD_F32:
+      launch_schur<float>(h, dagger ? 1 : 0, (float4*)out_e, (const float4*)in_e, (float4*)t, (const float2*)h->V32,
+                          (const float4*)h->He32, (const float4*)h->Hi32, nullptr, s);
+      break;
+    default:
+      launch_schur<float>(h, dagger ? 1 : 0, (uint4*)out_e, (const uint4*)in_e, (uint4*)t, (const uint32_t*)h->V16,
+                          (const float4*)h->He32, (const float4*)h->Hi32, nullptr, s);
+      break;
+  }
+  QXD_HIP(hipGetLastError());
+  return QXD_OK;
 }
 
 template <class T, class SPT, class LKT, class CLT>

@@ -429,5 +429,8 @@ qxd_status dfl_apply_internal(qxd_handle* h, qxd_dfl* d, int nc, int ncy, int nm
 bool sap_supported(const qxd_handle* h);
 qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, int eo, float4* out_e, const float4* in_e,
                               hipStream_t s, const float4* in_o = nullptr, float4* out_o = nullptr);
+// device address of the static workspace of qxd_dw_eo_schur_noalloc on
+// `device` (the current device), looked up once per device (dirac.hip)
+qxd_status scratch_resolve(int device);
 qxd_status qxd_schur_apply_mixed(qxd_handle* h, int dagger, float4* out_e, const float4* in_e, double* norm_slot,
                                  hipStream_t s);
