@@ -67,7 +67,8 @@ typedef enum {
   QXD_ENOCONV = 6,    /* the iteration limit was reached before the target */
   QXD_EHIP = 7,       /* a HIP runtime call failed */
   QXD_ESTATE = 8,     /* call out of order (e.g. apply before clover_invert) */
-  QXD_ESCRATCH = 9    /* the lattice needs more than the static workspace of a no-allocation call */
+  QXD_ESCRATCH = 9,   /* the lattice needs more than the static workspace of a no-allocation call */
+  QXD_EIO = 10        /* a file could not be written or read, or is not a valid network file */
 } qxd_status;
 
 typedef enum { QXD_F64 = 0, QXD_F32 = 1, QXD_BF16 = 2 } qxd_prec;
@@ -91,8 +92,6 @@ typedef struct {
   double max_norm;     /* largest max-abs entry of a 6x6 block */
   int64_t n_singular;  /* blocks with |pivot| < 1e-14 max-abs entry */
 } qxd_clover_stats;
-
-typedef enum { QXD_PRECOND_NONE = 0, QXD_PRECOND_NN = 1 } qxd_precond_kind;
 
 typedef struct {
   int nmx;             /* iteration limit (CG: iterations; FGCR: inner steps in total) */
@@ -388,6 +387,15 @@ qxd_status qxd_nn_set_skip(qxd_nn *net, double skip);
 /* Host pointers to QXD_NN_NWEIGHTS floats (synchronous). */
 qxd_status qxd_nn_set_weights(qxd_nn *net, const float *w);
 qxd_status qxd_nn_get_weights(qxd_nn *net, float *w);
+
+/* Save the network (FP32 master weights and the skip coefficient) to a file,
+ * or load one saved by qxd_nn_save into `net` (Adam state reset, as
+ * qxd_nn_set_weights).  The file holds an 8-byte tag, the weight count, the
+ * skip, an FNV-1a hash of the weight bytes, then the weights in the packed
+ * order above.  Synchronous.  QXD_EIO if the file cannot be written or read,
+ * or its tag, count, length or hash does not match. */
+qxd_status qxd_nn_save(qxd_nn *net, const char *path);
+qxd_status qxd_nn_load(qxd_nn *net, const char *path);
 
 /* out_e = |in_e| N(in_e / |in_e|): F32 even half fields. */
 qxd_status qxd_nn_apply(qxd_handle *h, qxd_nn *net, void *out_e, const void *in_e, void *stream);

@@ -21,12 +21,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.environ.get("QXD_LIBRARY", os.path.join(_HERE, "libqxd.so"))
 
 F64, F32, BF16 = 0, 1, 2
-PRECOND_NONE, PRECOND_NN = 0, 1
 NN_NWEIGHTS = 207360
 
 STATUS = {0: "QXD_OK", 1: "QXD_EINVAL", 2: "QXD_EGEOM", 3: "QXD_ENOMEM", 4: "QXD_ESINGULAR",
           5: "QXD_ENAN", 6: "QXD_ENOCONV", 7: "QXD_EHIP", 8: "QXD_ESTATE",
-          9: "QXD_ESCRATCH"}
+          9: "QXD_ESCRATCH", 10: "QXD_EIO"}
 
 
 class QxdError(RuntimeError):
@@ -118,6 +117,8 @@ _SIGNATURES = {
     "qxd_nn_set_weights": ([_P, _P], _I),
     "qxd_nn_set_skip": ([_P, _D], _I),
     "qxd_nn_get_weights": ([_P, _P], _I),
+    "qxd_nn_save": ([_P, ctypes.c_char_p], _I),
+    "qxd_nn_load": ([_P, ctypes.c_char_p], _I),
     "qxd_nn_apply": ([_P, _P, _P, _P, _P], _I),
     "qxd_sap_apply": ([_P, _I, _I, _I, _P, _P, _P], _I),
     "qxd_sap_apply_full": ([_P, _I, _I, _I, _P, _P, _P], _I),
@@ -395,6 +396,14 @@ def qxd_nn_get_weights(net):
     w = np.empty(NN_NWEIGHTS, dtype=np.float32)
     _check(load().qxd_nn_get_weights(net, w.ctypes.data), "qxd_nn_get_weights")
     return w
+
+
+def qxd_nn_save(net, path):
+    _check(load().qxd_nn_save(net, os.fsencode(path)), "qxd_nn_save")
+
+
+def qxd_nn_load(net, path):
+    _check(load().qxd_nn_load(net, os.fsencode(path)), "qxd_nn_load")
 
 
 def qxd_sap_apply(h, ncy, nmr, eo, out_e, in_e, stream=None):

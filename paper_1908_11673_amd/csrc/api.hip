@@ -16,6 +16,7 @@ extern "C" const char* qxd_status_string(qxd_status s) {
     case QXD_EHIP: return "QXD_EHIP";
     case QXD_ESTATE: return "QXD_ESTATE";
     case QXD_ESCRATCH: return "QXD_ESCRATCH";
+    case QXD_EIO: return "QXD_EIO";
   }
   return "QXD_UNKNOWN";
 }

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -962,6 +963,57 @@ extern "C" qxd_status qxd_nn_get_weights(qxd_nn* net, float* w) {
   if (!net || !w) return QXD_EINVAL;
   QXD_HIP(hipDeviceSynchronize());
   QXD_HIP(hipMemcpy(w, net->w, QXD_NN_NWEIGHTS * sizeof(float), hipMemcpyDeviceToHost));
+  return QXD_OK;
+}
+
+// Network file: 8-byte tag "QXDNNW01", int32 weight count, float32 skip,
+// uint32 FNV-1a hash of the weight bytes, uint32 zero, then the FP32 master
+// weights in the packed order of the header (host byte order, little-endian
+// on every machine this library runs on).
+static const char kNnTag[8] = {'Q', 'X', 'D', 'N', 'N', 'W', '0', '1'};
+
+static uint32_t fnv1a(const unsigned char* p, size_t n) {
+  uint32_t x = 2166136261u;
+  for (size_t i = 0; i < n; ++i) x = (x ^ p[i]) * 16777619u;
+  return x;
+}
+
+extern "C" qxd_status qxd_nn_save(qxd_nn* net, const char* path) {
+  if (!net || !path) return QXD_EINVAL;
+  std::vector<float> w(QXD_NN_NWEIGHTS);
+  QXD_HIP(hipDeviceSynchronize());
+  QXD_HIP(hipMemcpy(w.data(), net->w, QXD_NN_NWEIGHTS * sizeof(float), hipMemcpyDeviceToHost));
+  const size_t nb = w.size() * sizeof(float);
+  int32_t count = QXD_NN_NWEIGHTS;
+  uint32_t hash = fnv1a(reinterpret_cast<const unsigned char*>(w.data()), nb), zero = 0;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return QXD_EIO;
+  bool ok = std::fwrite(kNnTag, 1, 8, f) == 8 && std::fwrite(&count, 4, 1, f) == 1 &&
+            std::fwrite(&net->skip, 4, 1, f) == 1 && std::fwrite(&hash, 4, 1, f) == 1 &&
+            std::fwrite(&zero, 4, 1, f) == 1 && std::fwrite(w.data(), 1, nb, f) == nb;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? QXD_OK : QXD_EIO;
+}
+
+extern "C" qxd_status qxd_nn_load(qxd_nn* net, const char* path) {
+  if (!net || !path) return QXD_EINVAL;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return QXD_EIO;
+  char tag[8];
+  int32_t count = 0;
+  float skip = 0.f;
+  uint32_t hash = 0, zero = 1;
+  std::vector<float> w(QXD_NN_NWEIGHTS);
+  const size_t nb = w.size() * sizeof(float);
+  bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, kNnTag, 8) == 0 && std::fread(&count, 4, 1, f) == 1 &&
+            count == QXD_NN_NWEIGHTS && std::fread(&skip, 4, 1, f) == 1 && std::fread(&hash, 4, 1, f) == 1 &&
+            std::fread(&zero, 4, 1, f) == 1 && zero == 0 && std::fread(w.data(), 1, nb, f) == nb &&
+            std::fgetc(f) == EOF;
+  std::fclose(f);
+  if (!ok || fnv1a(reinterpret_cast<const unsigned char*>(w.data()), nb) != hash || !std::isfinite(skip))
+    return QXD_EIO;
+  QXD_TRY(qxd_nn_set_weights(net, w.data()));
+  net->skip = skip;
   return QXD_OK;
 }
 

@@ -8,13 +8,14 @@ call per field and pass; the Adam state lives in the network).
 """
 from __future__ import annotations
 
+import json
 import time
 
 import numpy as np
 
 from . import (Lattice, qxd_clover_build, qxd_clover_invert, qxd_nn_create, qxd_nn_destroy,
-               qxd_nn_get_weights, qxd_nn_harvest, qxd_nn_set_skip, qxd_nn_set_weights, qxd_nn_train,
-               qxd_set_flavour, qxd_set_gauge, train_params)
+               qxd_nn_get_weights, qxd_nn_harvest, qxd_nn_load, qxd_nn_save, qxd_nn_set_skip, qxd_nn_set_weights,
+               qxd_nn_train, qxd_set_flavour, qxd_set_gauge, train_params)
 
 SHAPES = [(24, 32), (32, 32), (32, 24)]
 
@@ -38,9 +39,13 @@ def _set_field(lat, U, A, flavour):
 
 
 def harvest_and_train(L, cstar, flavour, gauge_seeds, sigma_su3=0.2, sigma_u1=0.3, sources=10, pairs_per_source=10,
-                      epochs=8, lr=2e-4, batch=16, skip=None, init_seed=9, source_seed=3500, log=None):
+                      epochs=8, lr=2e-4, batch=16, skip=None, init_seed=9, source_seed=3500, log=None,
+                      pairs_per_field=None, max_sources=40):
     """Harvest pairs on the fields `gauge_seeds` of an L lattice and train a
-    network on them.  Returns (weights, skip, info)."""
+    network on them.  Each field gets `sources` Gaussian sources of up to
+    `pairs_per_source` pairs each; with `pairs_per_field` set, sources are
+    instead added (at most `max_sources`) until that many pairs are harvested
+    on the field.  Returns (weights, skip, info)."""
     import torch
     import synthgen as sg
     skip = 2.0 * flavour["kappa"] if skip is None else skip
@@ -48,20 +53,26 @@ def harvest_and_train(L, cstar, flavour, gauge_seeds, sigma_su3=0.2, sigma_u1=0.
     Ve = lat.Ve
     vphys = int(np.prod(L))
     fields, spans = [], []
-    n_max = len(gauge_seeds) * sources * pairs_per_source
+    per_field = pairs_per_field if pairs_per_field else sources * pairs_per_source
+    n_max = len(gauge_seeds) * per_field
     R = torch.zeros(n_max * 12 * Ve, dtype=torch.complex64, device="cuda")
     E = torch.zeros_like(R)
     t0 = time.perf_counter()
     n = 0
+    nsrc_used = []
     for f, gs in enumerate(gauge_seeds):
         U = torch.from_numpy(sg.gauge_su3(gs, sigma_su3, vphys)).cuda()
         A = torch.from_numpy(sg.gauge_u1(gs, sigma_u1, vphys)).cuda()
         fields.append((U, A))
         _set_field(lat, U, A, flavour)
         s0 = n
-        for src in range(sources):
+        src = 0
+        while src < (max_sources if pairs_per_field else sources) and n - s0 < per_field:
+            want = min(pairs_per_source, per_field - (n - s0))
             b = torch.from_numpy(sg.spinor(source_seed + 100 * f + src, lat.V)).cuda()
-            n += qxd_nn_harvest(lat.h, lat.pack(b), pairs_per_source, R[n * 12 * Ve:], E[n * 12 * Ve:])
+            n += qxd_nn_harvest(lat.h, lat.pack(b), want, R[n * 12 * Ve:], E[n * 12 * Ve:])
+            src += 1
+        nsrc_used.append(src)
         spans.append((s0, n))
     torch.cuda.synchronize()
     t_harvest = time.perf_counter() - t0
@@ -91,7 +102,8 @@ def harvest_and_train(L, cstar, flavour, gauge_seeds, sigma_su3=0.2, sigma_u1=0.
     qxd_nn_destroy(net)
     lat.close()
     del R, E
-    return w, skip, {"pairs": n, "harvest_s": t_harvest, "train_s": t_train, "loss_history": history}
+    return w, skip, {"pairs": n, "harvest_s": t_harvest, "train_s": t_train, "loss_history": history,
+                     "pairs_per_field": [b - a for a, b in spans], "sources_per_field": nsrc_used}
 
 
 def make_network(lat, weights, skip):
@@ -100,3 +112,26 @@ def make_network(lat, weights, skip):
     qxd_nn_set_weights(net, weights)
     qxd_nn_set_skip(net, skip)
     return net
+
+
+def save_network(prefix, net, meta):
+    """Write the network to `prefix`.qxdnn (qxd_nn_save: weights and skip) and
+    the JSON-serialisable `meta` (training seeds, configuration, losses) to
+    `prefix`.json."""
+    qxd_nn_save(net, prefix + ".qxdnn")
+    with open(prefix + ".json", "w") as f:
+        json.dump(meta, f, indent=1, sort_keys=True)
+
+
+def load_network(lat, prefix):
+    """A network on lattice `lat` read back from `prefix`.qxdnn, and its
+    metadata from `prefix`.json."""
+    net = qxd_nn_create(lat.h)
+    try:
+        qxd_nn_load(net, prefix + ".qxdnn")
+    except Exception:
+        qxd_nn_destroy(net)
+        raise
+    with open(prefix + ".json") as f:
+        meta = json.load(f)
+    return net, meta

@@ -436,3 +436,19 @@ def test_cg_on_c0_reaches_true_residual():
     x = o.eo_reconstruct(xe, b)
     assert it > 0
     assert np.linalg.norm(b - o.dirac(x)) / nb <= 1e-10
+
+
+@pytest.mark.parametrize("L,cstar", [((4, 4, 2, 2), 3), ((4, 2, 4, 2), 1), ((2, 4, 2, 4), 2)])
+def test_gauge_covariance_through_physical_fields(L, cstar):
+    """The gauge rotation the GPU tests apply to physical fields (the mirror
+    half then filled from them, as the library does) gives D' g psi = g D psi."""
+    from tests.gpu_common import gauge_rotate, rotate_spinor
+    o = make(L, cstar, seed=23, flav=FU)
+    U = sg.gauge_su3(23, 0.2, o.Vphys)
+    A = sg.gauge_u1(23, 0.3, o.Vphys)
+    U2, A2, g = gauge_rotate(o, U, A, FU["qhat"], 9)
+    o2 = oracle.Oracle(L, cstar)
+    o2.set_gauge_physical(U2, A2)
+    o2.set_flavour(**FU)
+    psi = sg.spinor(4, o.V)
+    assert rel(o2.dirac(rotate_spinor(g, psi)), rotate_spinor(g, o.dirac(psi))) < 1e-13
