@@ -137,12 +137,16 @@ qxd_status qxd_destroy(qxd_handle *h);
 qxd_status qxd_volume(const qxd_handle *h, int64_t *V, int64_t *Ve);
 
 /* Release the memory a set-up handle no longer needs for applying D, D_hat or
- * solving: the device copy of the physical gauge field and every solver and
- * Schur workspace (these are allocated again when next used).  Links, clover
- * blocks and their inverse stay.  Afterwards qxd_set_flavour and
+ * solving: the device copy of the physical gauge field, every solver and Schur
+ * workspace, and the FP32 / bf16 copies of the links and clover blocks (all
+ * of these are made again when next used; the copies from the FP64 links and
+ * blocks, which stay).  The handle makes a lower-precision copy only when a
+ * call first needs it (an FP32 or bf16 apply or solve, SAP, deflation), so an
+ * FP64-only computation never holds one.  Afterwards qxd_set_flavour and
  * qxd_clover_build return QXD_ESTATE until qxd_set_gauge is called again.  On
- * the largest lattices this is what leaves room for the solver vectors (about
- * 20 GB at 128 x 64^3 physical).  Synchronises the device. */
+ * the largest lattices this is what leaves room for the solver vectors (at
+ * 128 x 64^3 physical the FP64 operator alone is 97 GB).  Synchronises the
+ * device. */
 qxd_status qxd_trim(qxd_handle *h);
 
 /* Gauge fields on the physical lattice: U_phys [4][Vphys][3][3] complex128 (row,
@@ -153,8 +157,9 @@ qxd_status qxd_trim(qxd_handle *h);
 qxd_status qxd_set_gauge(qxd_handle *h, const double *U_phys, const double *A_phys, int on_device, void *stream);
 
 /* Select the flavour and build the combined links V(x,mu) = U(x,mu) z(x,mu)^qhat
- * (Sec. 2.3, covariant derivatives) on the extended lattice in every storage
- * precision.  Invalidates the clover until the next clover_build/invert.
+ * (Sec. 2.3, covariant derivatives) on the extended lattice in FP64 (FP32 and
+ * bf16 copies follow on first use).  Invalidates the clover until the next
+ * clover_build/invert.
  * QXD_ESTATE without a gauge field (none set yet, or released by qxd_trim). */
 qxd_status qxd_set_flavour(qxd_handle *h, const qxd_flavour *f, void *stream);
 
@@ -164,7 +169,8 @@ qxd_status qxd_set_flavour(qxd_handle *h, const qxd_flavour *f, void *stream);
 qxd_status qxd_clover_build(qxd_handle *h, void *stream);
 
 /* Invert the odd-site blocks (D_oo^-1 in Sec. 2.3's Schur complement) in FP64
- * by Gauss-Jordan elimination with partial pivoting, and store FP32 copies.
+ * by Gauss-Jordan elimination with partial pivoting (FP32 copies follow on
+ * first use).
  * Synchronous (reads the statistics back); QXD_ESINGULAR if any block is
  * numerically singular. */
 qxd_status qxd_clover_invert(qxd_handle *h, qxd_clover_stats *stats, void *stream);
@@ -187,7 +193,10 @@ qxd_status qxd_dw_eo_schur(qxd_handle *h, qxd_prec p, int dagger, void *out_e, c
  * buffer allocated on first use; the call allocates and frees nothing.
  * QXD_ESCRATCH when the half field (192 Ve bytes F64, 96 Ve F32, 48 Ve BF16)
  * exceeds the array: up to Ve = 349,525 in F64, 699,050 in F32, 1,398,101 in
- * BF16.  QXD_EINVAL when the current device is not the handle's.  All calls on
+ * BF16.  QXD_EINVAL when the current device is not the handle's; QXD_ESTATE
+ * before the clover inverse and, for F32 / BF16, while the handle holds no
+ * current copy of the operator in that precision (made by the first F32 /
+ * BF16 qxd_dw_eo_schur or solve, released by qxd_trim).  All calls on
  * one GPU share its array, which keeps the last call's contents: calls that
  * overlap in time on one GPU (several streams or host threads) race; serialise
  * them.  Nothing in the array needs to start at zero. */

@@ -105,9 +105,21 @@ extern "C" qxd_status qxd_trim(qxd_handle* h) {
     h->ws[i] = nullptr;
     h->ws_bytes[i] = 0;
   }
+  release_copies(h);
   h->has_gauge = false;
   h->sap_gen = 0;  // its block-order copies went with the workspaces
   return QXD_OK;
+}
+
+void release_copies(qxd_handle* h) {
+  void** ptrs[] = {reinterpret_cast<void**>(&h->V32), reinterpret_cast<void**>(&h->V16),
+                   reinterpret_cast<void**>(&h->He32), reinterpret_cast<void**>(&h->Ho32),
+                   reinterpret_cast<void**>(&h->Hi32)};
+  for (void** p : ptrs) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  h->copies = 0;
 }
 
 extern "C" qxd_status qxd_volume(const qxd_handle* h, int64_t* V, int64_t* Ve) {

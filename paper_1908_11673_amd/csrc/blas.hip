@@ -127,7 +127,7 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_sub_norm(VT* __restrict__ r, cons
   double a = 0.0;
   GRID_STRIDE(i, n) {
     VT v = wsub(ld_stream(&b[i]), ld_stream(&w[i]));
-    st_stream(&r[i], v);
+    if (r) st_stream(&r[i], v);  // r = nullptr: the norm only
     a += wnorm2(v);
   }
   double s = red_block(a, sh);

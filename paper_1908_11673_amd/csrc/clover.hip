@@ -345,11 +345,35 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_clover_cast(int Ve, const double2
 
 static qxd_status alloc_clover(qxd_handle* h) {
   if (h->He64) return QXD_OK;
-  size_t n64 = (size_t)36 * h->Ve * sizeof(double2), n32 = (size_t)18 * h->Ve * sizeof(float4);
+  size_t n64 = (size_t)36 * h->Ve * sizeof(double2);
   if (hipMalloc(&h->He64, n64) != hipSuccess || hipMalloc(&h->Ho64, n64) != hipSuccess ||
-      hipMalloc(&h->Hi64, n64) != hipSuccess || hipMalloc(&h->He32, n32) != hipSuccess ||
-      hipMalloc(&h->Ho32, n32) != hipSuccess || hipMalloc(&h->Hi32, n32) != hipSuccess)
+      hipMalloc(&h->Hi64, n64) != hipSuccess)
     return QXD_ENOMEM;
+  return QXD_OK;
+}
+
+qxd_status ensure_link_copies(qxd_handle* h, unsigned which, hipStream_t s);  // gauge.hip
+
+qxd_status ensure_copies(qxd_handle* h, unsigned which, hipStream_t s) {
+  QXD_TRY(ensure_link_copies(h, which, s));
+  const size_t n32 = (size_t)18 * h->Ve * sizeof(float4);
+  const int g18 = div_up(18 * h->Ve, QXD_BLOCK);
+  struct {
+    unsigned bit;
+    bool ready;
+    double2* src;
+    float4** dst;
+  } cl[3] = {{CP_HE32, h->has_clover, h->He64, &h->He32},
+             {CP_HO32, h->has_clover, h->Ho64, &h->Ho32},
+             {CP_HI32, h->has_inverse, h->Hi64, &h->Hi32}};
+  for (auto& c : cl) {
+    if (!(which & c.bit) || (h->copies & c.bit)) continue;
+    if (!c.ready) return QXD_ESTATE;
+    if (!*c.dst && hipMalloc(c.dst, n32) != hipSuccess) return QXD_ENOMEM;
+    hipLaunchKernelGGL(k_clover_cast, dim3(g18), dim3(QXD_BLOCK), 0, s, (int)h->Ve, c.src, *c.dst);
+    QXD_HIP(hipGetLastError());
+    h->copies |= c.bit;
+  }
   return QXD_OK;
 }
 
@@ -369,6 +393,7 @@ extern "C" qxd_status qxd_clover_build(qxd_handle* h, void* stream) {
   QXD_HIP(hipGetLastError());
   h->has_clover = true;
   h->has_inverse = false;
+  h->copies &= ~(CP_HE32 | CP_HO32 | CP_HI32);
   return QXD_OK;
 }
 
@@ -382,11 +407,7 @@ extern "C" qxd_status qxd_clover_invert(qxd_handle* h, qxd_clover_stats* stats, 
   InvStats st{d, d + 1, d + 2};
   hipLaunchKernelGGL(k_clover_invert, dim3(div_up(h->Ve, 64)), dim3(64), 0, s, (int)h->Ve, h->Ho64, h->Hi64, st);
   QXD_HIP(hipGetLastError());
-  int g18 = div_up(18 * h->Ve, QXD_BLOCK);
-  hipLaunchKernelGGL(k_clover_cast, dim3(g18), dim3(QXD_BLOCK), 0, s, (int)h->Ve, h->He64, h->He32);
-  hipLaunchKernelGGL(k_clover_cast, dim3(g18), dim3(QXD_BLOCK), 0, s, (int)h->Ve, h->Ho64, h->Ho32);
-  hipLaunchKernelGGL(k_clover_cast, dim3(g18), dim3(QXD_BLOCK), 0, s, (int)h->Ve, h->Hi64, h->Hi32);
-  QXD_HIP(hipGetLastError());
+  h->copies &= ~CP_HI32;
   unsigned long long res[3];
   QXD_HIP(hipMemcpyAsync(res, d, sizeof(res), hipMemcpyDeviceToHost, s));
   QXD_HIP(hipStreamSynchronize(s));

@@ -217,6 +217,7 @@ qxd_status qxd_schur_apply(qxd_handle* h, qxd_prec p, int dagger, void* out_e, c
                            hipStream_t s) {
   if (!h->has_inverse) return QXD_ESTATE;
   QXD_TRY(ensure_t(h, p));
+  if (p != QXD_F64) QXD_TRY(ensure_copies(h, (p == QXD_F32 ? CP_V32 : CP_V16) | CP_HE32 | CP_HI32, s));
   h->geo.tchunk = walk_chunk(h, p);
   switch (p) {
     case QXD_F64:
@@ -243,6 +244,7 @@ qxd_status qxd_schur_apply_mixed(qxd_handle* h, int dagger, float4* out_e, const
                                  hipStream_t s) {
   if (!h->has_inverse) return QXD_ESTATE;
   QXD_TRY(ensure_t(h, QXD_F32));
+  QXD_TRY(ensure_copies(h, CP_V16 | CP_HE32 | CP_HI32, s));
   h->geo.tchunk = walk_chunk(h, QXD_F32);
   launch_schur<float>(h, dagger, out_e, in_e, h->t32, (const uint32_t*)h->V16, (const float4*)h->He32,
                       (const float4*)h->Hi32, norm_slot, s);
@@ -294,6 +296,9 @@ extern "C" qxd_status qxd_dw_eo_schur_noalloc(qxd_handle* h, qxd_prec p, int dag
   if (p != QXD_F64 && p != QXD_F32 && p != QXD_BF16) return QXD_EINVAL;
   if (!h->has_inverse) return QXD_ESTATE;
   if (half_bytes(h, p) > (size_t)QXD_NOALLOC_SCRATCH_BYTES) return QXD_ESCRATCH;
+  // the FP32 / bf16 operator copies are made by an allocating call (not here)
+  const unsigned need = p == QXD_F64 ? 0u : (p == QXD_F32 ? CP_V32 : CP_V16) | CP_HE32 | CP_HI32;
+  if ((h->copies & need) != need) return QXD_ESTATE;
   int dev = -1;
   QXD_HIP(hipGetDevice(&dev));
   if (dev != h->device) return QXD_EINVAL;
@@ -342,7 +347,7 @@ extern "C" qxd_status qxd_dw_apply(qxd_handle* h, qxd_prec p, void* out, const v
       break;
     case QXD_F32:
     case QXD_BF16:
-      if (!h->has_inverse) return QXD_ESTATE;  // FP32 clover copies are made by clover_invert
+      QXD_TRY(ensure_copies(h, (p == QXD_F32 ? CP_V32 : CP_V16) | CP_HE32 | CP_HO32, s));
       if (p == QXD_F32)
         launch_dw<float>(h, (float4*)out, (const float4*)in, (const float2*)h->V32, (const float4*)h->He32,
                          (const float4*)h->Ho32, 6, s);

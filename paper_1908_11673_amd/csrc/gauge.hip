@@ -1,7 +1,8 @@
 // Gauge preparation on the extended lattice (Sec. 2.1 and 2.3 of arXiv:1908.11673):
 // the mirror half U(x + L1 e1) = U(x)*, A(x + L1 e1) = -A(x) is filled from the
 // physical half on the fly, and the combined links V(x,mu) = U(x,mu) z(x,mu)^qhat
-// with z = exp(i A) are written in the even-odd SoA layout in FP64, FP32 and BF16.
+// with z = exp(i A) are written in the even-odd SoA layout in FP64; the FP32 and
+// bf16 copies are made from them when first needed.
 #include "qxd_internal.hpp"
 
 // canonical physical site of extended coordinates, and whether x is on the mirror half
@@ -18,8 +19,7 @@ struct PhysExt {
 
 __global__ __launch_bounds__(QXD_BLOCK) void k_make_links(Geo g, PhysExt pe, const double2* __restrict__ U,
                                                            const double* __restrict__ A, int qhat,
-                                                           double2* __restrict__ V64, float2* __restrict__ V32,
-                                                           uint32_t* __restrict__ V16) {
+                                                           double2* __restrict__ V64) {
   int64_t t = (int64_t)blockIdx.x * QXD_BLOCK + threadIdx.x;
   int64_t total = 2 * (int64_t)g.Ve * 4;
   if (t >= total) return;
@@ -43,10 +43,42 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_make_links(Geo g, PhysExt pe, con
     cx<double> uu = mk(u.x, mirror ? -u.y : u.y);
     cx<double> v = uu * z;
     V64[base + k * Ve] = make_double2(v.re, v.im);
-    float fr = (float)v.re, fi = (float)v.im;
-    V32[base + k * Ve] = make_float2(fr, fi);
-    V16[base + k * Ve] = pack_bf16x2(fr, fi);
   }
+}
+
+// FP32 and bf16 copies of the links (each entry rounded to FP32, then to bf16)
+__global__ __launch_bounds__(QXD_BLOCK) void k_link_cast32(int64_t n, const double2* __restrict__ V64,
+                                                            float2* __restrict__ V32) {
+  int64_t t = (int64_t)blockIdx.x * QXD_BLOCK + threadIdx.x;
+  if (t >= n) return;
+  double2 v = V64[t];
+  V32[t] = make_float2((float)v.x, (float)v.y);
+}
+__global__ __launch_bounds__(QXD_BLOCK) void k_link_cast16(int64_t n, const double2* __restrict__ V64,
+                                                            uint32_t* __restrict__ V16) {
+  int64_t t = (int64_t)blockIdx.x * QXD_BLOCK + threadIdx.x;
+  if (t >= n) return;
+  double2 v = V64[t];
+  V16[t] = pack_bf16x2((float)v.x, (float)v.y);
+}
+
+qxd_status ensure_link_copies(qxd_handle* h, unsigned which, hipStream_t s) {
+  const int64_t n = (int64_t)2 * 4 * 9 * h->Ve;
+  if ((which & CP_V32) && !(h->copies & CP_V32)) {
+    if (!h->has_flavour) return QXD_ESTATE;
+    if (!h->V32 && hipMalloc(&h->V32, n * sizeof(float2)) != hipSuccess) return QXD_ENOMEM;
+    hipLaunchKernelGGL(k_link_cast32, dim3(div_up(n, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, n, h->V64, h->V32);
+    QXD_HIP(hipGetLastError());
+    h->copies |= CP_V32;
+  }
+  if ((which & CP_V16) && !(h->copies & CP_V16)) {
+    if (!h->has_flavour) return QXD_ESTATE;
+    if (!h->V16 && hipMalloc(&h->V16, n * sizeof(uint32_t)) != hipSuccess) return QXD_ENOMEM;
+    hipLaunchKernelGGL(k_link_cast16, dim3(div_up(n, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, n, h->V64, h->V16);
+    QXD_HIP(hipGetLastError());
+    h->copies |= CP_V16;
+  }
+  return QXD_OK;
 }
 
 extern "C" qxd_status qxd_set_gauge(qxd_handle* h, const double* U_phys, const double* A_phys, int on_device,
@@ -78,18 +110,15 @@ extern "C" qxd_status qxd_set_flavour(qxd_handle* h, const qxd_flavour* f, void*
   if (!(f->kappa > 0.0) || !(f->invqel > 0.0)) return QXD_EINVAL;
   hipStream_t s = as_stream(stream);
   size_t nl = (size_t)2 * 4 * 9 * h->Ve;
-  if (!h->V64) {
-    if (hipMalloc(&h->V64, nl * sizeof(double2)) != hipSuccess) return QXD_ENOMEM;
-    if (hipMalloc(&h->V32, nl * sizeof(float2)) != hipSuccess) return QXD_ENOMEM;
-    if (hipMalloc(&h->V16, nl * sizeof(uint32_t)) != hipSuccess) return QXD_ENOMEM;
-  }
+  if (!h->V64 && hipMalloc(&h->V64, nl * sizeof(double2)) != hipSuccess) return QXD_ENOMEM;
+  h->copies = 0;
   PhysExt pe;
   for (int m = 0; m < 4; ++m) pe.L[m] = h->g.L[m];
   // without C* there is no mirror half: x1 never reaches L1
   pe.Vphys = h->Vphys;
   int64_t total = 2 * h->Ve * 4;
   hipLaunchKernelGGL(k_make_links, dim3(div_up(total, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, h->geo, pe,
-                     reinterpret_cast<const double2*>(h->Uphys), h->Aphys, f->qhat, h->V64, h->V32, h->V16);
+                     reinterpret_cast<const double2*>(h->Uphys), h->Aphys, f->qhat, h->V64);
   QXD_HIP(hipGetLastError());
   h->fl = *f;
   h->has_flavour = true;

@@ -362,6 +362,7 @@ struct qxd_handle {
   double* scal_host = nullptr;  // pinned mirror
   size_t npartial = 0;        // doubles in `partial`
   bool tchunk_env = false;    // walk chunk fixed by QXD_TILE_CHUNK
+  unsigned copies = 0;        // CP_* bits: lower-precision operator copies that are current
   uint64_t setup_gen = 0;     // bumped whenever the links or clover blocks are rebuilt
   uint64_t sap_gen = 0;       // SAP's block-order copies: 2 setup_gen + slot order (0: none)
   // solver workspaces (grow-only), indexed by role
@@ -429,6 +430,15 @@ qxd_status dfl_apply_internal(qxd_handle* h, qxd_dfl* d, int nc, int ncy, int nm
 bool sap_supported(const qxd_handle* h);
 qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, int eo, float4* out_e, const float4* in_e,
                               hipStream_t s, const float4* in_o = nullptr, float4* out_o = nullptr);
+// Lower-precision copies of the operator (links V in FP32 and bf16, clover
+// blocks H_e, H_o, H_o^-1 in FP32) are made from the FP64 ones when a call
+// first needs them and released by qxd_trim, so that a handle holds only the
+// copies the computations it runs use.  ensure_copies makes the `which` copies
+// current (QXD_ESTATE if their FP64 source is not set up, QXD_ENOMEM).
+enum : unsigned { CP_V32 = 1u, CP_V16 = 2u, CP_HE32 = 4u, CP_HO32 = 8u, CP_HI32 = 16u };
+qxd_status ensure_copies(qxd_handle* h, unsigned which, hipStream_t s);
+void release_copies(qxd_handle* h);
+
 // device address of the static workspace of qxd_dw_eo_schur_noalloc on
 // `device` (the current device), looked up once per device (dirac.hip)
 qxd_status scratch_resolve(int device);

@@ -390,6 +390,7 @@ qxd_status sap_pack(qxd_handle* h, int eo, float2** Vb, float4** Cb, float4** CI
   // the copies are tagged 2 setup_gen + eo
   const uint64_t tag = 2 * h->setup_gen + (uint64_t)eo;
   if (h->sap_gen != tag) {
+    QXD_TRY(ensure_copies(h, CP_V32 | CP_HE32 | CP_HO32 | CP_HI32, s));
     auto pack = eo ? k_sap_pack<true> : k_sap_pack<false>;
     hipLaunchKernelGGL(pack, dim3(nblk), dim3(kSapSites), 0, s, g, *sb, reinterpret_cast<const float2*>(h->V32),
                        reinterpret_cast<const float4*>(h->He32), reinterpret_cast<const float4*>(h->Ho32),

@@ -34,10 +34,9 @@ qxd_status read_scal(qxd_handle* h, int first, int count, hipStream_t s) {
 qxd_status true_residual(qxd_handle* h, const double2* x, const double2* b, double nb, double* res, hipStream_t s) {
   size_t nfull = (size_t)24 * h->Ve;
   double2* w = (double2*)ws_get(h, W_FULL0, nfull * sizeof(double2));
-  double2* r = (double2*)ws_get(h, W_FULL1, nfull * sizeof(double2));
-  if (!w || !r) return QXD_ENOMEM;
+  if (!w) return QXD_ENOMEM;
   QXD_TRY(qxd_dw_apply(h, QXD_F64, w, x, s));
-  blas_sub_norm<double2>(h, r, b, w, nfull, h->scal + S_RT, s);
+  blas_sub_norm<double2>(h, nullptr, b, w, nfull, h->scal + S_RT, s);
   QXD_TRY(read_scal(h, S_RT, 1, s));
   *res = std::sqrt(h->scal_host[S_RT]) / nb;
   return QXD_OK;
@@ -440,8 +439,8 @@ qxd_status solve_fgcr(qxd_handle* h, const qxd_solver_params* prm, qxd_nn* net, 
   size_t b64 = n64 * sizeof(double2);
   double2 *bh = (double2*)ws_get(h, W_BH, b64), *xe = (double2*)ws_get(h, W_XE, b64);
   double2 *r = (double2*)ws_get(h, W_R, b64), *w = (double2*)ws_get(h, W_W, b64);
-  double2* e64 = (double2*)ws_get(h, W_E64, b64);
-  if (!bh || !xe || !r || !w || !e64) return QXD_ENOMEM;
+  double2* e64 = mode == 0 ? (double2*)ws_get(h, W_E64, b64) : nullptr;  // the FP64 FGCR's correction
+  if (!bh || !xe || !r || !w || (mode == 0 && !e64)) return QXD_ENOMEM;
   float4 *r32 = nullptr, *e32 = nullptr;
   if (mode != 0) {
     r32 = (float4*)ws_get(h, W_R32, n32 * sizeof(float4));

@@ -63,3 +63,25 @@ def test_noalloc_schur_rejects_a_lattice_beyond_the_static_workspace():
     torch.cuda.synchronize()
     assert torch.equal(ref, got) and float(ref.abs().max()) > 0
     lat.close()
+
+
+def test_noalloc_schur_needs_the_precision_copies_made_by_an_allocating_call():
+    """The FP32 / bf16 operator copies are made by the first allocating call of
+    that precision; before it (and after qxd_trim released them) the
+    no-allocation call reports QXD_ESTATE instead of allocating."""
+    o, lat, _ = make_pair((4, 2, 4, 4), 3, FD, sigma=0.3, su1=0.4, seed=8)
+    lib = qxd.load()
+    P = qxd.ctypes.c_void_p
+    for prec in (qxd.F32, qxd.BF16):
+        src = lat.pack(to_dev(sg.spinor(9, o.V)), prec)
+        inp = src[: src.numel() // 2].clone()
+        out = torch.zeros_like(inp)
+        assert lib.qxd_dw_eo_schur_noalloc(lat.h, prec, 0, P(out.data_ptr()), P(inp.data_ptr()), None) == 8
+        ref = torch.zeros_like(inp)
+        qxd.qxd_dw_eo_schur(lat.h, prec, 0, ref, inp)
+        qxd.qxd_dw_eo_schur_noalloc(lat.h, prec, 0, out, inp)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, out)
+    qxd.qxd_trim(lat.h)
+    assert lib.qxd_dw_eo_schur_noalloc(lat.h, qxd.BF16, 0, P(out.data_ptr()), P(inp.data_ptr()), None) == 8
+    lat.close()
