@@ -37,6 +37,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Dw GB/s & %HBM roofline; time-to-1e-10 residual, mixed+learned vs FP64 CG"
 HBM_PEAK_GBS = 8000.0
 REALS_PER_VE = 552
+# bf16 storage: links 288 reals and spinors 120 reals at 2 bytes, clover blocks 144 reals at 4 bytes
+BF16_BYTES_PER_VE = (288 + 120) * 2 + 144 * 4
 
 
 def log(msg):
@@ -52,20 +54,31 @@ def make_fields(w):
     return U, A
 
 
-def cpu_baseline(w, U, A, flav, seconds=15.0):
-    """Oracle D_hat on a bounded sample of even sites of the same lattice."""
-    import oracle
-    import synthgen as sg
-    o = oracle.Oracle(w["L"], w["cstar"])
-    o.set_gauge_physical(U, A)
-    o.set_flavour(**flav, cache=False, blocks=False)
-    psi = sg.spinor(w["source_seed"], o.V)
-    par = o.parity()
-    psi[par == 1] = 0
-    even = np.nonzero(par == 0)[0]
-    rng = np.random.default_rng(0)
-    n = 64
-    done, t_tot = 0, 0.0
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of this process (the oracle's parallel
+    loops); returns the previous count."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    old = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(int(n))
+    return old
+
+
+def _oracle_rate(o, psi, even, seconds, seed):
+    """Oracle D_hat on batches of random even sites for about `seconds`:
+    sites done and the time they took."""
+    rng = np.random.default_rng(seed)
+    n, done, t_tot = 64, 0, 0.0
     while t_tot < seconds:
         sites = rng.choice(even, size=n, replace=False)
         t0 = time.perf_counter()
@@ -73,10 +86,64 @@ def cpu_baseline(w, U, A, flav, seconds=15.0):
         t_tot += time.perf_counter() - t0
         done += n
         n = min(2 * n, 4096)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    gbs = done * REALS_PER_VE * 8 / t_tot / 1e9
-    return {"value": gbs, "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": "%d random even sites of the same lattice (FP64 D_hat, oracle as is), %.1f s" % (done, t_tot)}
+    return done, t_tot
+
+
+def cpu_baseline(w, U, A, flav, seconds=15.0):
+    """The FP64 oracle's D_hat on a bounded sample of even sites of the same
+    lattice, with its site clover blocks and their inverses precomputed (the
+    oracle's cache; the set-up is timed apart and not in the rate): all host
+    threads for about half the time, then one thread; plus the oracle's CG solve
+    of the 8 x 4^3 lattice to the same 1e-10 residual (one thread)."""
+    import oracle
+    import synthgen as sg
+    try:  # numpy's BLAS threads spin after each call and starve the oracle's OpenMP loops
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(1, user_api="blas")
+    except ImportError:
+        limit = None
+    threads = _omp_threads(os.cpu_count() or 1)
+    _omp_threads(threads)
+    o = oracle.Oracle(w["L"], w["cstar"])
+    o.set_gauge_physical(U, A)
+    t0 = time.perf_counter()
+    o.set_flavour(**flav, cache=True)
+    setup_s = time.perf_counter() - t0
+    psi = sg.spinor(w["source_seed"], o.V)
+    par = o.parity()
+    psi[par == 1] = 0
+    even = np.nonzero(par == 0)[0]
+    done, t_all = _oracle_rate(o, psi, even, seconds / 2, 0)
+    old = _omp_threads(1)
+    done1, t_one = _oracle_rate(o, psi, even, seconds / 2, 1)
+    _omp_threads(old)
+    gbs = done * REALS_PER_VE * 8 / t_all / 1e9
+    gbs1 = done1 * REALS_PER_VE * 8 / t_one / 1e9
+    # the oracle's FP64 CG on the small workload (8 x 4^3, C* in x1), true residual 1e-10
+    w0 = sg.WORKLOADS["c0"]
+    o0 = oracle.Oracle(w0["L"], w0["cstar"])
+    vp = int(np.prod(w0["L"]))
+    o0.set_gauge_physical(sg.gauge_su3(w0["gauge_seed"], w0["sigma_su3"], vp), sg.gauge_u1(w0["gauge_seed"],
+                                                                                            w0["sigma_u1"], vp))
+    o0.set_flavour(**flav)
+    b0 = sg.spinor(w0["source_seed"], o0.V)
+    old = _omp_threads(1)  # 512 even sites: one thread is fastest
+    t0 = time.perf_counter()
+    bh = o0.eo_source(b0)
+    xe, it0, _ = o0.cg(bh, 1e-10 * np.linalg.norm(b0))
+    x0 = o0.eo_reconstruct(xe, b0)
+    c0_ms = (time.perf_counter() - t0) * 1e3
+    _omp_threads(old)
+    res0 = float(np.linalg.norm(b0 - o0.dirac(x0)) / np.linalg.norm(b0))
+    if limit is not None:
+        limit.unregister()
+    return {"value": gbs, "unit": "GB/s", "cores": threads, "kind": "oracle", "cpu_model": _cpu_model(),
+            "one_core_gbs": gbs1,
+            "sample": "FP64 D_hat of the oracle as is on random even sites of the same lattice (%d sites in %.1f s "
+                      "on %d threads, %d sites in %.1f s on 1 thread), site blocks precomputed in %.1f s" % (
+                          done, t_all, threads, done1, t_one, setup_s),
+            "c0_cg": {"ms": round(c0_ms, 1), "iterations": it0, "true_residual": res0, "threads": 1,
+                      "lattice": "8x4^3 physical, C* 1"}}
 
 
 def main():
@@ -87,8 +154,9 @@ def main():
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 128 x 64^3 time-to-solution leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--nn-fields", type=int, default=10, help="fields for the network training (0: no network)")
+    ap.add_argument("--nn-fields", type=int, default=20, help="fields for the network training (0: no network)")
     ap.add_argument("--nn-epochs", type=int, default=8)
     ap.add_argument("--legs", default="", help="comma-separated solve legs to run (default: all)")
     args = ap.parse_args()
@@ -97,6 +165,7 @@ def main():
               "halo exchange over xGMI is designed, not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    t_start = time.perf_counter()
     import torch
     import paper_1908_11673_amd as qxd
     import synthgen as sg
@@ -177,6 +246,27 @@ def main():
     ach64 = REALS_PER_VE * 8 * Ve / (ms64 * 1e-3) / 1e9
     ach32 = REALS_PER_VE * 4 * Ve / (ms32 * 1e-3) / 1e9
     log("D_hat FP64 %.3f ms (%.0f GB/s), FP32 %.3f ms (%.0f GB/s)" % (ms64, ach64, ms32, ach32))
+    # bf16 storage: links and spinors in bfloat16, clover blocks FP32
+    in16 = [qxd.field(Ve, qxd.BF16) for _ in range(nbuf)]
+    out16 = [qxd.field(Ve, qxd.BF16) for _ in range(nbuf)]
+    for i in range(nbuf):
+        full = qxd.field(Ve, qxd.BF16, full=True)
+        qxd.qxd_pack(lats[0].h, qxd.BF16, full, lats[0].unpack(
+            torch.cat([ins[qxd.F64][i], torch.zeros_like(ins[qxd.F64][i])])))
+        in16[i].copy_(full[:full.numel() // 2])
+        del full
+    for i in range(10):
+        qxd.qxd_dw_eo_schur(lats[0].h, qxd.BF16, 0, out16[i % nbuf], in16[i % nbuf], sptr)
+    n16 = 100
+    e0.record(stream)
+    for i in range(n16):
+        qxd.qxd_dw_eo_schur(lats[0].h, qxd.BF16, 0, out16[i % nbuf], in16[i % nbuf], sptr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms16 = e0.elapsed_time(e1) / n16
+    ach16 = BF16_BYTES_PER_VE * Ve / (ms16 * 1e-3) / 1e9
+    log("D_hat bf16 storage %.3f ms (%.0f GB/s)" % (ms16, ach16))
+    del in16, out16
 
     copy_gbs = copy_calibration(torch)
     log("plain copy of 1.5 GiB (not cache resident): %.0f GB/s read+write" % copy_gbs)
@@ -206,6 +296,9 @@ def main():
                      "traffic": recorded_traffic("dhat_f64") if args.workload == "c1" else None,
                      "kernel": "D_hat FP64 (k_schur1 + k_schur2)", "ms_per_launch": round(ms64, 4)},
         "dhat_fp32": {"ms": round(ms32, 4), "achieved_gbs": round(ach32, 1), "frac": round(ach32 / HBM_PEAK_GBS, 4)},
+        "dhat_bf16": {"ms": round(ms16, 4), "achieved_gbs": round(ach16, 1), "frac": round(ach16 / HBM_PEAK_GBS, 4),
+                      "bytes_per_even_site": BF16_BYTES_PER_VE,
+                      "storage": "links and spinors bfloat16, clover blocks FP32"},
         "copy_kernel_gbs": round(copy_gbs, 1),
     }
 
@@ -213,13 +306,22 @@ def main():
         del ins, outs
         torch.cuda.empty_cache()
         only = tuple(t for t in args.legs.split(",") if t)
-        train = not only or "fgcr_f32_nn_in_f64" in only
-        result["time_to_solution"] = solve_leg(qxd, torch, lats, w, flavours, args.nn_fields if train else 0,
-                                               args.nn_epochs, big, only)
+        train = (not only or "fgcr_f32_nn_in_f64" in only or "learned" in only) and args.nn_fields > 0
+        nets = train_networks(qxd, flavours, args.nn_fields, args.nn_epochs) if train else None
+        if nets and not big and (not only or "learned" in only):
+            result["learned_c3"] = learned_leg(qxd, torch, flavours, nets)
+        result["time_to_solution"] = solve_leg(qxd, torch, lats, w, flavours, nets, big, only)
         if not big and (not only or "shifted" in only):
             result["shifted_solves"] = shifted_leg(qxd, torch, lats, w, flavours)
         if not big and (not only or "deflation" in only):
             result["deflation"] = deflation_leg(qxd, torch, lats, w, flavours, U, A)
+
+    if not args.no_c4 and not big and not args.no_solve and (not only or "c4" in only):
+        for lat in lats:
+            lat.close()
+        lats = []
+        torch.cuda.empty_cache()
+        result["time_to_solution_c4"] = c4_leg(qxd, torch, nets, t_start)
 
     if not args.no_cpu_baseline and not big:  # the oracle would hold 60 GB of host fields at 128 x 64^3
         log("cpu baseline (oracle) ...")
@@ -414,37 +516,107 @@ def deflation_leg(qxd, torch, lats, w, flavours, U, A):
     return out
 
 
-def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, only=()):
-    """Time to a true FP64 residual 1e-10 on the benchmark lattice, one Gaussian
-    source per flavour: FP64 CG against defect-correction CG and FGCR with FP32
-    and bf16-link inner solves, FP32-inner FGCR preconditioned by SAP (two
-    cycles, 8 plain minimal-residual steps per 4^4 block), and FP32-inner FGCR preconditioned
-    by a network trained (per flavour) on pairs harvested from seeded 32 x 16^3
-    fields with the same statistics."""
+def train_networks(qxd, flavours, nn_fields, nn_epochs, pairs_per_field=100):
+    """One network per flavour, trained on `pairs_per_field` (residual, error)
+    pairs harvested on each of the 32 x 16^3 fields 3000 .. 3000 + nn_fields - 1
+    (the learned form's training set: 20 fields x 100 pairs)."""
     import synthgen as sg
     from paper_1908_11673_amd import learned
     c3 = sg.WORKLOADS["c3"]
+    nets = []
+    for flav in flavours:
+        wts, skip, info = learned.harvest_and_train(c3["L"], c3["cstar"], flav,
+                                                    gauge_seeds=list(range(3000, 3000 + nn_fields)),
+                                                    sigma_su3=c3["sigma_su3"], sigma_u1=c3["sigma_u1"],
+                                                    pairs_per_field=pairs_per_field, epochs=nn_epochs)
+        meta = {"pairs": info["pairs"], "harvest_s": round(info["harvest_s"], 2), "train_s": round(info["train_s"], 2),
+                "loss_first_last": [round(info["loss_history"][0], 4), round(info["loss_history"][-1], 4)],
+                "lattice": "32x16^3 physical, C* 3", "fields": nn_fields, "pairs_per_field_target": pairs_per_field,
+                "epochs": nn_epochs, "skip": skip}
+        log("qhat %+d network: %d pairs on %d fields, harvest %.1f s, train %.1f s, loss %.3f -> %.3f" % (
+            flav["qhat"], info["pairs"], nn_fields, info["harvest_s"], info["train_s"], info["loss_history"][0],
+            info["loss_history"][-1]))
+        nets.append((wts, skip, meta))
+    return nets
+
+
+NN_HELD_OUT = tuple(range(3100, 3110))  # held-out 32 x 16^3 fields of the learned-form evaluation
+
+
+def learned_leg(qxd, torch, flavours, nets):
+    """The learned form on its own lattice: per flavour, FGCR preconditioned by
+    the trained network against plain FGCR (both FP32 inner, FP64 defect
+    correction) and FP64 CG, to the FP64 true residual 1e-10 on each held-out
+    32 x 16^3 field (one Gaussian source each; median of 3 timed solves)."""
+    import synthgen as sg
+    from paper_1908_11673_amd import learned
+    c3 = sg.WORKLOADS["c3"]
+    L, cstar = c3["L"], c3["cstar"]
+    vphys = int(np.prod(L))
     out = {}
-    b = sg.spinor(w["source_seed"] + 1, lats[0].V)
-    for lat, flav, name in zip(lats, flavours, ("qhat-2", "qhat+4")):
+    lat = qxd.Lattice(L, cstar)
+    for flav, (wts, skip, meta) in zip(flavours, nets):
+        name = "qhat%+d" % flav["qhat"]
+        net = learned.make_network(lat, wts, skip)
+        rows = {"network_fgcr": [], "plain_fgcr": [], "cg_f64": []}
+        for k, gs in enumerate(NN_HELD_OUT):
+            lat.setup(sg.gauge_su3(gs, c3["sigma_su3"], vphys), sg.gauge_u1(gs, c3["sigma_u1"], vphys), flav)
+            bd = lat.pack(torch.from_numpy(sg.spinor(3600 + k, lat.V)).cuda())
+            x = lat.field(qxd.F64, full=True)
+            prm = qxd.solver_params(res=1e-10, inner_prec=qxd.F32)
+            legs = (("network_fgcr", lambda: qxd.qxd_solve_fgcr(lat.h, prm, net, x, bd, check=False)),
+                    ("plain_fgcr", lambda: qxd.qxd_solve_fgcr(lat.h, prm, None, x, bd, check=False)),
+                    ("cg_f64", lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, check_every=8), x, bd,
+                                                        check=False)))
+            for tag, fn in legs:
+                fn()  # warm-up
+                times = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st = fn()
+                    torch.cuda.synchronize()
+                    times.append((time.perf_counter() - t0) * 1e3)
+                rows[tag].append({"field": gs, "steps": st["inner_it"], "ms": round(float(np.median(times)), 2),
+                                  "status": st["status"], "true_residual": st["true_residual"],
+                                  "fell_back": st["fell_back"]})
+        qxd.qxd_nn_destroy(net)
+        summary = {t: {"steps_mean": round(float(np.mean([r["steps"] for r in v])), 1),
+                       "ms_mean": round(float(np.mean([r["ms"] for r in v])), 2)} for t, v in rows.items()}
+        out[name] = {"training": meta, "held_out_fields": list(NN_HELD_OUT), "summary": summary, "per_field": rows}
+        log("%s learned form at 32x16^3 over %d held-out fields: network FGCR %.1f steps %.1f ms, plain FGCR %.1f "
+            "steps %.1f ms, FP64 CG %.1f it %.1f ms" % (
+                name, len(NN_HELD_OUT), summary["network_fgcr"]["steps_mean"], summary["network_fgcr"]["ms_mean"],
+                summary["plain_fgcr"]["steps_mean"], summary["plain_fgcr"]["ms_mean"],
+                summary["cg_f64"]["steps_mean"], summary["cg_f64"]["ms_mean"]))
+    lat.close()
+    return out
+
+
+def solve_leg(qxd, torch, lats, w, flavours, nets, big=False, only=(), b=None):
+    """Time to a true FP64 residual 1e-10 on the benchmark lattice, one Gaussian
+    source per flavour: FP64 CG against defect-correction CG and FGCR with FP32
+    and bf16-link inner solves, FP32-inner FGCR preconditioned by SAP (two
+    cycles, 8 plain minimal-residual steps per 4^4 block), and FP32-inner FGCR
+    preconditioned by the flavour's network (`nets`, trained on 32 x 16^3
+    fields with the same statistics; the network is local, so its weights
+    apply on any lattice).  `big` (the 128 x 64^3 lattice): one timed solve per
+    leg, no SAP legs, the CG workspaces released before FGCR, and FGCR with the
+    largest restart length of 12, 10, ..., 4 whose directions fit beside the
+    operator."""
+    import synthgen as sg
+    from paper_1908_11673_amd import learned
+    out = {}
+    if b is None:
+        b = sg.spinor(w["source_seed"] + 1, lats[0].V)
+    for i, (lat, flav) in enumerate(zip(lats, flavours)):
+        name = "qhat%+d" % flav["qhat"]
         res = {}
         net = None
-        if nn_fields > 0:
-            t0 = time.perf_counter()
-            wts, skip, info = learned.harvest_and_train(c3["L"], c3["cstar"], flav,
-                                                        gauge_seeds=list(range(3000, 3000 + nn_fields)),
-                                                        sigma_su3=w["sigma_su3"], sigma_u1=w["sigma_u1"], sources=8,
-                                                        pairs_per_source=10, epochs=nn_epochs)
+        if nets:
+            wts, skip, meta = nets[i]
             net = learned.make_network(lat, wts, skip)
-            res["network_training"] = {"pairs": info["pairs"], "harvest_s": round(info["harvest_s"], 2),
-                                       "train_s": round(info["train_s"], 2),
-                                       "loss_first_last": [round(info["loss_history"][0], 4),
-                                                           round(info["loss_history"][-1], 4)],
-                                       "lattice": "32x16^3 physical, C* 3", "fields": nn_fields,
-                                       "epochs": nn_epochs, "skip": skip}
-            log("%s network: %d pairs, harvest %.1f s, train %.1f s, loss %.3f -> %.3f" % (
-                name, info["pairs"], info["harvest_s"], info["train_s"], info["loss_history"][0],
-                info["loss_history"][-1]))
+            res["network_training"] = meta
         bd = lat.pack(torch.from_numpy(b).cuda())
         torch.cuda.empty_cache()  # the library allocates its solver vectors itself
         x = lat.field(qxd.F64, full=True)
@@ -453,32 +625,39 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, on
             return lambda: qxd.qxd_solve_cg(lat.h, qxd.solver_params(res=1e-10, inner_prec=inner, check_every=8), x,
                                             bd, check=False)
 
-        # at 128 x 64^3 the 2 nkv FGCR directions must fit beside the operator: nkv 4
-        nkv = 4 if big else 16
+        nkv = [12 if big else 16]
 
-        def fgcr(inner, network=None, sap_ncy=0, sap_nmr=8, sap_plain=0):
-            prm = qxd.solver_params(res=1e-10, inner_prec=inner, sap_ncy=sap_ncy, sap_nmr=sap_nmr,
-                                    sap_plain=sap_plain, nkv=nkv)
-            return lambda: qxd.qxd_solve_fgcr(lat.h, prm, network, x, bd, check=False)
+        def fgcr(inner, network=None, sap_ncy=0, sap_nmr=8, sap_plain=0, nmx=100000):
+            return lambda: qxd.qxd_solve_fgcr(
+                lat.h, qxd.solver_params(res=1e-10, inner_prec=inner, sap_ncy=sap_ncy, sap_nmr=sap_nmr,
+                                         sap_plain=sap_plain, nkv=nkv[0], nmx=nmx), network, x, bd, check=False)
 
         legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16))]
-        legs.append(("fgcr_f32_in_f64", fgcr(qxd.F32)))
+        legs.append(("fgcr_f32_in_f64", (qxd.F32, None)))
         if not big:  # the SAP block copies do not fit beside the 128 x 64^3 operator and FGCR's directions
-            legs += [("fgcr_bf16links_in_f64", fgcr(qxd.BF16)),
-                     ("fgcr_f32_sap_in_f64", fgcr(qxd.F32, sap_ncy=SAP_NCY, sap_nmr=SAP_NMR, sap_plain=SAP_PLAIN)),
-                     ("fgcr_f32_sap_eo55_in_f64", fgcr(qxd.F32, sap_ncy=5, sap_nmr=5, sap_plain=0))]
+            legs += [("fgcr_bf16links_in_f64", (qxd.BF16, None)),
+                     ("fgcr_f32_sap_in_f64", (qxd.F32, None, SAP_NCY, SAP_NMR, SAP_PLAIN)),
+                     ("fgcr_f32_sap_eo55_in_f64", (qxd.F32, None, 5, 5, 0))]
         if net is not None:
-            legs.append(("fgcr_f32_nn_in_f64", fgcr(qxd.F32, net)))
+            legs.append(("fgcr_f32_nn_in_f64", (qxd.F32, net)))
         trimmed = False
         for tag, fn in legs:
             if only and tag not in only:
                 continue
-            if big and tag.startswith("fgcr"):
-                if not trimmed:  # drop the CG legs' workspaces before FGCR allocates its own
-                    qxd.qxd_trim(lat.h)
-                    torch.cuda.empty_cache()
-                    trimmed = True
-                fn()  # untimed: the first call allocates the 2 nkv directions
+            if tag.startswith("fgcr"):
+                spec = fn
+                fn = fgcr(*spec)
+                if big:
+                    if not trimmed:  # drop the CG legs' workspaces before FGCR allocates its own
+                        qxd.qxd_trim(lat.h)
+                        torch.cuda.empty_cache()
+                        trimmed = True
+                    # untimed one-step call: allocates the 2 nkv directions (fewer if they do not fit)
+                    while fgcr(*spec, nmx=1)()["status"] == 3 and nkv[0] > 4:
+                        qxd.qxd_trim(lat.h)
+                        nkv[0] -= 2
+                        log("%s %s: directions do not fit, restart length %d" % (name, tag, nkv[0]))
+                    fn = fgcr(*spec)
             times = []
             for rep in range(1 if big else 3):
                 torch.cuda.synchronize()
@@ -491,12 +670,65 @@ def solve_leg(qxd, torch, lats, w, flavours, nn_fields, nn_epochs, big=False, on
                         "nn_applies": st["nn_applies"], "sap_applies": st["sap_applies"], "fell_back": st["fell_back"],
                         "true_residual": st["true_residual"]}
             if tag.startswith("fgcr"):
-                res[tag]["nkv"] = nkv
+                res[tag]["nkv"] = nkv[0]
             log("solve %s %s: %.1f ms, %d it, res %.2e, status %d" % (name, tag, np.median(times), st["inner_it"],
                                                                        st["true_residual"], st["status"]))
         if net is not None:
             qxd.qxd_nn_destroy(net)
         out[name] = res
+    return out
+
+
+C4_LEGS = {"qhat-2": ("cg_f64", "cg_f32_in_f64", "fgcr_f32_in_f64", "fgcr_f32_nn_in_f64"),
+           "qhat+4": ("cg_f64", "cg_f32_in_f64")}
+C4_BUDGET_S = 220.0  # bench seconds elapsed after which the up-type solves at 128 x 64^3 are left out
+
+
+def c4_leg(qxd, torch, nets, t_start):
+    """Time to the FP64 true residual 1e-10 at the largest one-GPU share, the
+    128 x 64^3 physical lattice with C* in three directions (extended 128 x 128
+    x 64 x 64, 67,108,864 sites), both flavours one after the other on one
+    handle; one Gaussian source, one timed solve each.  Down-type: FP64 CG
+    against defect-correction CG (FP32 inner), FP32-inner FGCR and
+    network-preconditioned FP32-inner FGCR.  Up-type: FP64 CG against
+    defect-correction CG only; at this volume its operator needs about 1650 CG
+    iterations, FGCR with the restart lengths whose directions fit (12 and
+    less) stalls near 1e-6 after 2500 steps, and the network gains no steps for
+    this flavour at any volume measured.  The handle holds the FP64 operator
+    (97 GB) and only the lower-precision copies the running solve uses.  The
+    up-type solves are left out if the bench has already run C4_BUDGET_S
+    seconds (about 200 s of solves)."""
+    import synthgen as sg
+    w4 = sg.WORKLOADS["c4"]
+    t0 = time.perf_counter()
+    U, A = make_fields(w4)
+    lat = qxd.Lattice(w4["L"], w4["cstar"])
+    b = sg.spinor(w4["source_seed"], lat.V)
+    log("c4 fields and source generated in %.1f s" % (time.perf_counter() - t0))
+    out = {}
+    flavours = [sg.FLAVOURS["d"], sg.FLAVOURS["u"]]
+    for i, flav in enumerate(flavours):
+        name = "qhat%+d" % flav["qhat"]
+        if name == "qhat+4" and time.perf_counter() - t_start > C4_BUDGET_S:
+            log("c4 %s left out: %.0f s of bench elapsed" % (name, time.perf_counter() - t_start))
+            out[name] = {"skipped": "bench time budget (%.0f s elapsed)" % (time.perf_counter() - t_start)}
+            continue
+        t0 = time.perf_counter()
+        st = lat.setup(U, A, flav)
+        qxd.qxd_trim(lat.h)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        log("c4 qhat %+d set up in %.1f s (min pivot %.4f)" % (flav["qhat"], setup_s, st["min_pivot"]))
+        res = solve_leg(qxd, torch, [lat], w4, [flav], [nets[i]] if nets else None, big=True, only=C4_LEGS[name],
+                        b=b)
+        torch.cuda.empty_cache()
+        res[name]["setup_s"] = round(setup_s, 2)
+        res[name]["min_pivot"] = st["min_pivot"]
+        out[name] = res[name]
+        qxd.qxd_trim(lat.h)
+    lat.close()
+    del U, A, b
+    out["lattice"] = "128x64^3 physical, C* 3 (extended 128x128x64x64)"
     return out
 
 
