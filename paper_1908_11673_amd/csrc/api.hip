@@ -56,6 +56,7 @@ extern "C" qxd_status qxd_create(const qxd_geom* g, qxd_handle** out) {
   h->geo.L3h = g->L[3] / 2;
   h->geo.Ve = (int)h->Ve;
   h->geo.tchunk = 8;
+  if (const char* e = std::getenv("QXD_SCHUR_SLICES")) h->slices_env = std::atoi(e);
   if (const char* e = std::getenv("QXD_TILE_CHUNK")) {
     h->geo.tchunk = std::atoi(e);
     h->tchunk_env = true;

@@ -40,7 +40,9 @@ template <class T, class SPT, class LKT, class CLT, bool DAG>
 __global__ __launch_bounds__(QXD_BLOCK) void k_schur1(Geo g, const SPT* __restrict__ in_e, SPT* __restrict__ t_o,
                                                       const LKT* __restrict__ Ve_l, const LKT* __restrict__ Vo_l,
                                                       const CLT* __restrict__ Hi) {
-  int h = site_tile(blockIdx.x, gridDim.x, g.tchunk) * QXD_BLOCK + threadIdx.x;
+  int tile = site_tile(blockIdx.x, gridDim.x, g.tchunk) + g.tile0;
+  if (g.ntile && tile >= g.ntile) tile -= g.ntile;
+  int h = tile * QXD_BLOCK + threadIdx.x;
   if (h >= g.Ve) return;
   cx<T> acc[12], out[12];
   hop_site<DAG, T>(g, 1, h, in_e, Vo_l, Ve_l, acc);
@@ -55,7 +57,8 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_schur2(Geo g, const SPT* __restri
                                                       const LKT* __restrict__ Ve_l, const LKT* __restrict__ Vo_l,
                                                       const CLT* __restrict__ He, double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
-  int tile = site_tile(blockIdx.x, gridDim.x, g.tchunk);
+  int tile = site_tile(blockIdx.x, gridDim.x, g.tchunk) + g.tile0;
+  if (g.ntile && tile >= g.ntile) tile -= g.ntile;
   int h = tile * QXD_BLOCK + threadIdx.x;
   double n2 = 0.0;
   if (h < g.Ve) {
@@ -172,33 +175,90 @@ static qxd_status ensure_t(qxd_handle* h, qxd_prec p) {
 }
 
 
+// Pass-by-pass order of the Schur launches.  Both passes are memory bound and
+// pass 2 reads back t_o and psi_e, which pass 1 wrote and read.  Run over the
+// whole lattice, pass 1 moves several times the last-level cache between the
+// two, so pass 2 finds neither there.  Instead the time slices are taken in
+// chunks of C: pass 1 on chunk k, then pass 2 on the slices whose three t_o
+// time neighbours are now all written (chunk k shifted back by one slice), and
+// at the end pass 2 on the last slice and slice 0 (time is periodic).  Every
+// site is computed exactly as in the two-launch order (bit-identical results,
+// partial sums indexed by tile), and pass 2 reads t_o and psi_e while they are
+// still in the 256 MB last-level cache.  C is the largest divisor of the time
+// extent (at most half of it) for which the t_o and psi_e of a chunk take at
+// most 256 MB, used when it is at least 8 slices; otherwise (and for bf16
+// storage, and where the slices are not whole tiles) two plain launches.
+// Measured at 64x64x32x32 (128 tiles a slice): FP64 D_hat 1.786 ms in two
+// launches, 1.698 ms with chunks of 16 slices (9 launches), 1.737 with 8;
+// FP32 0.899 -> 0.885 (32 slices); bf16 storage 0.755 -> 0.773, so off.  At
+// 128x128x64x64 a slice holds 100 MB per array and chunks of 2, 4 or 8 slices
+// are slower (FP64 27.6 ms -> 29.1-30.0).  Running pass 2 of a chunk on a side
+// stream beside pass 1 of the next was slower as well (1.772 ms).
+static int schur_slices(const qxd_handle* h, qxd_prec p) {
+  const int64_t S = h->Ve / h->geo.Le0;  // half sites per time slice
+  if (S % QXD_BLOCK) return 0;
+  int c = h->slices_env;
+  if (c < 0) {
+    const double per_slice = (double)S * 2 * (p == QXD_F64 ? 192 : p == QXD_F32 ? 96 : 48);
+    c = (int)(256e6 / per_slice);
+  }
+  if (c > h->geo.Le0 / 2) c = h->geo.Le0 / 2;
+  while (c >= 2 && h->geo.Le0 % c) --c;
+  if (h->slices_env < 0 && (c < 8 || p == QXD_BF16)) return 0;
+  return c >= 2 ? c : 0;
+}
+
 template <class T, class SPT, class LKT, class CLT>
 static void launch_schur(qxd_handle* h, int dagger, SPT* out, const SPT* in, SPT* t, const LKT* V, const CLT* He,
-                         const CLT* Hi, double* norm_slot, hipStream_t s) {
+                         const CLT* Hi, double* norm_slot, int slices, hipStream_t s) {
   const size_t lk_half = (size_t)4 * 9 * h->Ve;
   const LKT* Ve_l = V;
   const LKT* Vo_l = V + lk_half;
-  int G = div_up(h->Ve, QXD_BLOCK);
-  if (dagger)
-    hipLaunchKernelGGL((k_schur1<T, SPT, LKT, CLT, true>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, in, t, Ve_l, Vo_l, Hi);
-  else
-    hipLaunchKernelGGL((k_schur1<T, SPT, LKT, CLT, false>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, in, t, Ve_l, Vo_l, Hi);
-  if (norm_slot) {
+  const int G = div_up(h->Ve, QXD_BLOCK);
+  Geo g = h->geo;
+  auto pass1 = [&](int tile0, int n) {
+    g.tile0 = tile0;
     if (dagger)
-      hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, true, true>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, t, in, out,
-                         Ve_l, Vo_l, He, h->partial);
+      hipLaunchKernelGGL((k_schur1<T, SPT, LKT, CLT, true>), dim3(n), dim3(QXD_BLOCK), 0, s, g, in, t, Ve_l, Vo_l, Hi);
     else
-      hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, false, true>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, t, in, out,
-                         Ve_l, Vo_l, He, h->partial);
-    launch_final_sum(h->partial, G, 1, G, norm_slot, s);
+      hipLaunchKernelGGL((k_schur1<T, SPT, LKT, CLT, false>), dim3(n), dim3(QXD_BLOCK), 0, s, g, in, t, Ve_l, Vo_l, Hi);
+  };
+  auto pass2 = [&](int tile0, int n) {
+    g.tile0 = tile0;
+    if (n <= 0) return;
+    if (norm_slot) {
+      if (dagger)
+        hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, true, true>), dim3(n), dim3(QXD_BLOCK), 0, s, g, t, in, out,
+                           Ve_l, Vo_l, He, h->partial);
+      else
+        hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, false, true>), dim3(n), dim3(QXD_BLOCK), 0, s, g, t, in, out,
+                           Ve_l, Vo_l, He, h->partial);
+    } else {
+      if (dagger)
+        hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, true, false>), dim3(n), dim3(QXD_BLOCK), 0, s, g, t, in, out,
+                           Ve_l, Vo_l, He, nullptr);
+      else
+        hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, false, false>), dim3(n), dim3(QXD_BLOCK), 0, s, g, t, in, out,
+                           Ve_l, Vo_l, He, nullptr);
+    }
+  };
+  if (slices == 0) {
+    g.ntile = 0;
+    pass1(0, G);
+    pass2(0, G);
   } else {
-    if (dagger)
-      hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, true, false>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, t, in, out,
-                         Ve_l, Vo_l, He, nullptr);
-    else
-      hipLaunchKernelGGL((k_schur2<T, SPT, LKT, CLT, false, false>), dim3(G), dim3(QXD_BLOCK), 0, s, h->geo, t, in, out,
-                         Ve_l, Vo_l, He, nullptr);
+    const int T1 = (int)(h->Ve / h->geo.Le0 / QXD_BLOCK);  // tiles per time slice
+    const int C = slices, nchunk = h->geo.Le0 / slices;
+    g.ntile = G;
+    pass1(0, C * T1);
+    pass2(T1, (C - 2) * T1);
+    for (int k = 1; k < nchunk; ++k) {
+      pass1(k * C * T1, C * T1);
+      pass2((k * C - 1) * T1, C * T1);
+    }
+    pass2((h->geo.Le0 - 1) * T1, 2 * T1);
   }
+  if (norm_slot) launch_final_sum(h->partial, G, 1, G, norm_slot, s);
 }
 
 // Workgroup walk for the Schur passes (site_tile): windows of K tiles per XCD.
@@ -222,15 +282,15 @@ qxd_status qxd_schur_apply(qxd_handle* h, qxd_prec p, int dagger, void* out_e, c
   switch (p) {
     case QXD_F64:
       launch_schur<double>(h, dagger, (double2*)out_e, (const double2*)in_e, h->t64, (const double2*)h->V64,
-                           (const double2*)h->He64, (const double2*)h->Hi64, norm_slot, s);
+                           (const double2*)h->He64, (const double2*)h->Hi64, norm_slot, schur_slices(h, p), s);
       break;
     case QXD_F32:
       launch_schur<float>(h, dagger, (float4*)out_e, (const float4*)in_e, h->t32, (const float2*)h->V32,
-                          (const float4*)h->He32, (const float4*)h->Hi32, norm_slot, s);
+                          (const float4*)h->He32, (const float4*)h->Hi32, norm_slot, schur_slices(h, p), s);
       break;
     case QXD_BF16:
       launch_schur<float>(h, dagger, (uint4*)out_e, (const uint4*)in_e, h->t16, (const uint32_t*)h->V16,
-                          (const float4*)h->He32, (const float4*)h->Hi32, norm_slot, s);
+                          (const float4*)h->He32, (const float4*)h->Hi32, norm_slot, schur_slices(h, p), s);
       break;
     default:
       return QXD_EINVAL;
@@ -247,7 +307,7 @@ qxd_status qxd_schur_apply_mixed(qxd_handle* h, int dagger, float4* out_e, const
   QXD_TRY(ensure_copies(h, CP_V16 | CP_HE32 | CP_HI32, s));
   h->geo.tchunk = walk_chunk(h, QXD_F32);
   launch_schur<float>(h, dagger, out_e, in_e, h->t32, (const uint32_t*)h->V16, (const float4*)h->He32,
-                      (const float4*)h->Hi32, norm_slot, s);
+                      (const float4*)h->Hi32, norm_slot, schur_slices(h, QXD_F32), s);
   QXD_HIP(hipGetLastError());
   return QXD_OK;
 }
@@ -309,15 +369,15 @@ extern "C" qxd_status qxd_dw_eo_schur_noalloc(qxd_handle* h, qxd_prec p, int dag
   switch (p) {
     case QXD_F64:
       launch_schur<double>(h, dagger ? 1 : 0, (double2*)out_e, (const double2*)in_e, (double2*)t,
-                           (const double2*)h->V64, (const double2*)h->He64, (const double2*)h->Hi64, nullptr, s);
+                           (const double2*)h->V64, (const double2*)h->He64, (const double2*)h->Hi64, nullptr, schur_slices(h, p), s);
       break;
     case QXD_F32:
       launch_schur<float>(h, dagger ? 1 : 0, (float4*)out_e, (const float4*)in_e, (float4*)t, (const float2*)h->V32,
-                          (const float4*)h->He32, (const float4*)h->Hi32, nullptr, s);
+                          (const float4*)h->He32, (const float4*)h->Hi32, nullptr, schur_slices(h, p), s);
       break;
     default:
       launch_schur<float>(h, dagger ? 1 : 0, (uint4*)out_e, (const uint4*)in_e, (uint4*)t, (const uint32_t*)h->V16,
-                          (const float4*)h->He32, (const float4*)h->Hi32, nullptr, s);
+                          (const float4*)h->He32, (const float4*)h->Hi32, nullptr, schur_slices(h, p), s);
       break;
   }
   QXD_HIP(hipGetLastError());

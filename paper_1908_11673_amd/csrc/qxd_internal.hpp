@@ -67,6 +67,7 @@ struct Geo {
   int L3h;                 // Le3 / 2
   int Ve;                  // half volume
   int tchunk;              // workgroup -> lattice tile order (see site_tile)
+  int tile0, ntile;        // Schur passes: launch covers tiles tile0 + [0, grid) mod ntile (ntile 0: tile0 = 0)
 };
 
 // Coordinates of the site with half index h in parity p.
@@ -362,6 +363,7 @@ struct qxd_handle {
   double* scal_host = nullptr;  // pinned mirror
   size_t npartial = 0;        // doubles in `partial`
   bool tchunk_env = false;    // walk chunk fixed by QXD_TILE_CHUNK
+  int slices_env = -1;        // time slices per Schur chunk fixed by QXD_SCHUR_SLICES (-1: by size)
   unsigned copies = 0;        // CP_* bits: lower-precision operator copies that are current
   uint64_t setup_gen = 0;     // bumped whenever the links or clover blocks are rebuilt
   uint64_t sap_gen = 0;       // SAP's block-order copies: 2 setup_gen + slot order (0: none)
