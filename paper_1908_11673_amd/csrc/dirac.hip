@@ -180,8 +180,9 @@ static qxd_status ensure_t(qxd_handle* h, qxd_prec p) {
 // whole lattice, pass 1 moves several times the last-level cache between the
 // two, so pass 2 finds neither there.  Instead the time slices are taken in
 // chunks of C: pass 1 on chunk k, then pass 2 on the slices whose three t_o
-// time neighbours are now all written (chunk k shifted back by one slice), and
-// at the end pass 2 on the last slice and slice 0 (time is periodic).  Every
+// time neighbours are now all written (chunk k shifted back by one slice).
+// Time is periodic: the first chunk starts at the last slice, so that the
+// pass 2 after the last chunk covers the remaining C + 2 slices in one launch.  Every
 // site is computed exactly as in the two-launch order (bit-identical results,
 // partial sums indexed by tile), and pass 2 reads t_o and psi_e while they are
 // still in the 256 MB last-level cache.  C is the largest divisor of the time
@@ -250,13 +251,14 @@ static void launch_schur(qxd_handle* h, int dagger, SPT* out, const SPT* in, SPT
     const int T1 = (int)(h->Ve / h->geo.Le0 / QXD_BLOCK);  // tiles per time slice
     const int C = slices, nchunk = h->geo.Le0 / slices;
     g.ntile = G;
-    pass1(0, C * T1);
-    pass2(T1, (C - 2) * T1);
+    // chunk k: slices kC - 1 .. (k+1)C - 2 (chunk 0 starts at the last slice);
+    // after it, pass 2 on kC - 2 .. (k+1)C - 3, after the last on the rest
+    pass1((h->geo.Le0 - 1) * T1, C * T1);
+    pass2(0, (C - 2) * T1);
     for (int k = 1; k < nchunk; ++k) {
-      pass1(k * C * T1, C * T1);
-      pass2((k * C - 1) * T1, C * T1);
+      pass1((k * C - 1) * T1, C * T1);
+      pass2((k * C - 2) * T1, (k + 1 < nchunk ? C : C + 2) * T1);
     }
-    pass2((h->geo.Le0 - 1) * T1, 2 * T1);
   }
   if (norm_slot) launch_final_sum(h->partial, G, 1, G, norm_slot, s);
 }
