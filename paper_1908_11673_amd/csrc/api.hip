@@ -1,5 +1,6 @@
 // Handle management of libqxd.
 #include <cstdlib>
+#include <cstring>
 #include <new>
 
 #include "qxd_internal.hpp"
@@ -57,6 +58,7 @@ extern "C" qxd_status qxd_create(const qxd_geom* g, qxd_handle** out) {
   h->geo.Ve = (int)h->Ve;
   h->geo.tchunk = 8;
   if (const char* e = std::getenv("QXD_SCHUR_SLICES")) h->slices_env = std::atoi(e);
+  if (const char* e = std::getenv("QXD_SCHUR_STORES")) h->geo.plain_st = std::strcmp(e, "plain") == 0;
   if (const char* e = std::getenv("QXD_TILE_CHUNK")) {
     h->geo.tchunk = std::atoi(e);
     h->tchunk_env = true;

@@ -35,6 +35,16 @@ __device__ __forceinline__ double sp_norm2(const cx<T> s[12]) {
   return a;
 }
 
+// The outputs of both passes (t_o, chi) are stored either plainly or with the
+// non-temporal hint, chosen at run time (Geo::plain_st, QXD_SCHUR_STORES=plain);
+// every configuration measured is fastest with the non-temporal stores, also in
+// the chunked order where pass 2 reads t_o back soon (FP64 1.70 against
+// 1.73 ms).  With the choice in the kernels the compiler schedules the
+// bf16-storage passes differently: pass 1 issues its last direction's twelve
+// loads together instead of one at a time and needs 146 registers instead of
+// 271; bf16 D_hat at 64x64x32x32 went 0.755 -> 0.627 ms (the choice in pass 1)
+// -> 0.565 ms (in both passes), the FP64 and FP32 passes unchanged.
+
 // pass 1: t_o = H_o^-1 hop_oe(g5? psi_e)
 template <class T, class SPT, class LKT, class CLT, bool DAG>
 __global__ __launch_bounds__(QXD_BLOCK) void k_schur1(Geo g, const SPT* __restrict__ in_e, SPT* __restrict__ t_o,
@@ -47,7 +57,8 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_schur1(Geo g, const SPT* __restri
   cx<T> acc[12], out[12];
   hop_site<DAG, T>(g, 1, h, in_e, Vo_l, Ve_l, acc);
   clover_mul<T>(Hi, g.Ve, h, acc, out);
-  sp_store_nt(t_o, g.Ve, h, out);
+  if (g.plain_st) sp_store(t_o, g.Ve, h, out);
+  else sp_store_nt(t_o, g.Ve, h, out);
 }
 
 // pass 2: out_e = H_e psi_e - (1/4) g5? hop_eo(t_o); optional block partials of |out|^2
@@ -69,7 +80,8 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_schur2(Geo g, const SPT* __restri
     clover_mul<T>(He, g.Ve, h, s, c);
 #pragma unroll
     for (int k = 0; k < 12; ++k) c[k] = c[k] - T(0.25) * acc[k];
-    sp_store_nt(out_e, g.Ve, h, c);
+    if (g.plain_st) sp_store(out_e, g.Ve, h, c);
+    else sp_store_nt(out_e, g.Ve, h, c);
     if (NORM) n2 = sp_norm2(c);
   }
   if (NORM) {
@@ -182,19 +194,19 @@ static qxd_status ensure_t(qxd_handle* h, qxd_prec p) {
 // chunks of C: pass 1 on chunk k, then pass 2 on the slices whose three t_o
 // time neighbours are now all written (chunk k shifted back by one slice).
 // Time is periodic: the first chunk starts at the last slice, so that the
-// pass 2 after the last chunk covers the remaining C + 2 slices in one launch.  Every
-// site is computed exactly as in the two-launch order (bit-identical results,
-// partial sums indexed by tile), and pass 2 reads t_o and psi_e while they are
-// still in the 256 MB last-level cache.  C is the largest divisor of the time
+// pass 2 after the last chunk covers the remaining C + 2 slices in one launch.
+// Every site is computed exactly as in the two-launch order (bit-identical
+// results, partial sums indexed by tile), and pass 2 reads t_o and psi_e while
+// they are still in the 256 MB last-level cache.  C is the largest divisor of the time
 // extent (at most half of it) for which the t_o and psi_e of a chunk take at
-// most 256 MB, used when it is at least 8 slices; otherwise (and for bf16
-// storage, and where the slices are not whole tiles) two plain launches.
-// Measured at 64x64x32x32 (128 tiles a slice): FP64 D_hat 1.786 ms in two
-// launches, 1.698 ms with chunks of 16 slices (9 launches), 1.737 with 8;
-// FP32 0.899 -> 0.885 (32 slices); bf16 storage 0.755 -> 0.773, so off.  At
-// 128x128x64x64 a slice holds 100 MB per array and chunks of 2, 4 or 8 slices
-// are slower (FP64 27.6 ms -> 29.1-30.0).  Running pass 2 of a chunk on a side
-// stream beside pass 1 of the next was slower as well (1.772 ms).
+// most 256 MB, used when it is at least 8 slices; otherwise (and where the
+// slices are not whole tiles) two plain launches.  Measured at 64x64x32x32
+// (128 tiles a slice): FP64 D_hat 1.786 ms in two launches, 1.688 ms with chunks
+// of 16 slices (8 launches), 1.737 with 8; FP32 0.899 -> 0.862 (32 slices);
+// bf16 storage 0.564 -> 0.556 (32 slices).  At 128x128x64x64 a slice holds
+// 100 MB per array and chunks of 2, 4 or 8 slices are slower (FP64 27.6 ms ->
+// 29.1-30.0).  Running pass 2 of a chunk on a side stream beside pass 1 of the
+// next was slower as well (1.772 ms).
 static int schur_slices(const qxd_handle* h, qxd_prec p) {
   const int64_t S = h->Ve / h->geo.Le0;  // half sites per time slice
   if (S % QXD_BLOCK) return 0;
@@ -205,7 +217,7 @@ static int schur_slices(const qxd_handle* h, qxd_prec p) {
   }
   if (c > h->geo.Le0 / 2) c = h->geo.Le0 / 2;
   while (c >= 2 && h->geo.Le0 % c) --c;
-  if (h->slices_env < 0 && (c < 8 || p == QXD_BF16)) return 0;
+  if (h->slices_env < 0 && c < 8) return 0;
   return c >= 2 ? c : 0;
 }
 

@@ -68,6 +68,7 @@ struct Geo {
   int Ve;                  // half volume
   int tchunk;              // workgroup -> lattice tile order (see site_tile)
   int tile0, ntile;        // Schur passes: launch covers tiles tile0 + [0, grid) mod ntile (ntile 0: tile0 = 0)
+  int plain_st;            // Schur passes store t_o and chi plainly (1) or with the non-temporal hint (0, default)
 };
 
 // Coordinates of the site with half index h in parity p.
