@@ -97,7 +97,7 @@ typedef struct {
   int nmx;             /* iteration limit (CG: iterations; FGCR: inner steps in total) */
   double res;          /* target true relative residual |b - D x| / |b| (full lattice) */
   int inner_prec;      /* qxd_prec of the inner CG / FGCR operator (F64: no defect correction) */
-  double inner_res;    /* relative residual reduction asked of each inner solve */
+  double inner_res;    /* relative residual reduction asked of each inner solve (0: 1e-5 for F32, 1e-3 for BF16) */
   int nkv;             /* FGCR restart length (1..24; 0: 16) */
   int max_outer;       /* defect-correction steps limit */
   int check_every;     /* CG: read the residual back every this many iterations */

@@ -259,7 +259,7 @@ def qxd_unpack(h, prec, aos, soa, stream=None):
     _check(load().qxd_unpack(h, int(prec), _ptr(aos), _ptr(soa), _stream(stream)), "qxd_unpack")
 
 
-def solver_params(nmx=100000, res=1e-10, inner_prec=F32, inner_res=1e-5, nkv=16, max_outer=100, check_every=4,
+def solver_params(nmx=100000, res=1e-10, inner_prec=F32, inner_res=0.0, nkv=16, max_outer=100, check_every=4,
                   fallback_after=50, sap_ncy=0, sap_nmr=4, sap_plain=0, dfl_nc=0):
     return qxd_solver_params(int(nmx), float(res), int(inner_prec), float(inner_res), int(nkv), int(max_outer),
                              int(check_every), int(fallback_after), int(sap_ncy), int(sap_nmr), int(sap_plain),

@@ -58,6 +58,37 @@ __device__ inline bool wfinite(double2 a) { return isfinite(a.x) && isfinite(a.y
 // non-temporal hint (ld_stream, st_stream).
 #define GRID_STRIDE(i, n) for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
 
+// Traversal in rounds with QXD_UNR elements in flight per thread: in a round
+// workgroup b takes the QXD_UNR * blockDim contiguous elements that start at
+// round_start + b QXD_UNR blockDim, thread t the elements t, t + blockDim, ...
+// of them, and all loads of the round (load(i) returns an element's words) are
+// issued before the first element is used (use(i, words)).  The elements after
+// the last full round go one at a time in a plain grid-stride loop.  (With a
+// plain grid-stride loop, even unrolled, the compiler waits for an element's
+// loads before issuing the next element's; with the elements of a round a grid
+// apart, each wave reads several distant regions at once, which measured
+// slower than contiguous rounds.)  The order is fixed, so the reductions stay
+// reproducible.
+#define QXD_UNR 4
+template <class Load, class Use>
+__device__ __forceinline__ void stream_for(size_t n, Load load, Use use) {
+  const size_t B = blockDim.x, span = (size_t)gridDim.x * QXD_UNR * B;  // elements per round
+  size_t start = 0;
+  for (; start + span <= n; start += span) {
+    const size_t i0 = start + (size_t)blockIdx.x * QXD_UNR * B + threadIdx.x;
+    decltype(load(i0)) w[QXD_UNR];
+#pragma unroll
+    for (int u = 0; u < QXD_UNR; ++u) w[u] = load(i0 + u * B);
+#pragma unroll
+    for (int u = 0; u < QXD_UNR; ++u) use(i0 + u * B, w[u]);
+  }
+  for (size_t i = start + (size_t)blockIdx.x * B + threadIdx.x; i < n; i += (size_t)gridDim.x * B) use(i, load(i));
+}
+template <class VT>
+struct W2 {
+  VT a, b;
+};
+
 // ---- kernels ---------------------------------------------------------------
 
 __global__ __launch_bounds__(QXD_BLOCK) void k_final_sum(const double* __restrict__ partial, int n, int nvals,
@@ -75,7 +106,7 @@ template <class VT>
 __global__ __launch_bounds__(QXD_BLOCK) void k_norm2(const VT* __restrict__ x, size_t n, double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
   double a = 0.0;
-  GRID_STRIDE(i, n) a += wnorm2(ld_stream(&x[i]));
+  stream_for(n, [&](size_t i) { return ld_stream(&x[i]); }, [&](size_t, VT v) { a += wnorm2(v); });
   double s = red_block(a, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
@@ -85,7 +116,8 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_cdot(const VT* __restrict__ x, co
                                                     double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
   double re = 0.0, im = 0.0;
-  GRID_STRIDE(i, n) wcdot(ld_stream(&x[i]), ld_stream(&y[i]), re, im);
+  stream_for(n, [&](size_t i) { return W2<VT>{ld_stream(&x[i]), ld_stream(&y[i])}; },
+             [&](size_t, W2<VT> v) { wcdot(v.a, v.b, re, im); });
   double s = red_block(re, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
   s = red_block(im, sh);
@@ -100,12 +132,17 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_cg_xr(VT* __restrict__ x, VT* __r
   __shared__ double sh[QXD_BLOCK / 64];
   double alpha = scal[i_zz] / scal[i_ww];
   double a = 0.0;
-  GRID_STRIDE(i, n) {
-    st_stream(&x[i], wcaxpy(ld_stream(&x[i]), alpha, 0.0, ld_stream(&p[i])));
-    VT rr = wcaxpy(ld_stream(&r[i]), -alpha, 0.0, ld_stream(&w[i]));
-    st_stream(&r[i], rr);
-    a += wnorm2(rr);
-  }
+  struct W4 {
+    VT x, p, r, w;
+  };
+  stream_for(
+      n, [&](size_t i) { return W4{ld_stream(&x[i]), ld_stream(&p[i]), ld_stream(&r[i]), ld_stream(&w[i])}; },
+      [&](size_t i, W4 v) {
+        st_stream(&x[i], wcaxpy(v.x, alpha, 0.0, v.p));
+        VT rr = wcaxpy(v.r, -alpha, 0.0, v.w);
+        st_stream(&r[i], rr);
+        a += wnorm2(rr);
+      });
   double s = red_block(a, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
@@ -115,7 +152,8 @@ template <class VT>
 __global__ __launch_bounds__(QXD_BLOCK) void k_cg_p(VT* __restrict__ p, const VT* __restrict__ z, size_t n,
                                                     const double* __restrict__ scal, int i_new, int i_old) {
   double beta = scal[i_new] / scal[i_old];
-  GRID_STRIDE(i, n) st_stream(&p[i], wcaxpy(ld_stream(&z[i]), beta, 0.0, ld_stream(&p[i])));
+  stream_for(n, [&](size_t i) { return W2<VT>{ld_stream(&z[i]), ld_stream(&p[i])}; },
+             [&](size_t i, W2<VT> v) { st_stream(&p[i], wcaxpy(v.a, beta, 0.0, v.b)); });
 }
 
 // r = b - w; partial |r|^2
@@ -125,50 +163,72 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_sub_norm(VT* __restrict__ r, cons
                                                         double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
   double a = 0.0;
-  GRID_STRIDE(i, n) {
-    VT v = wsub(ld_stream(&b[i]), ld_stream(&w[i]));
-    if (r) st_stream(&r[i], v);  // r = nullptr: the norm only
-    a += wnorm2(v);
-  }
+  stream_for(n, [&](size_t i) { return W2<VT>{ld_stream(&b[i]), ld_stream(&w[i])}; },
+             [&](size_t i, W2<VT> bw) {
+               VT v = wsub(bw.a, bw.b);
+               if (r) st_stream(&r[i], v);  // r = nullptr: the norm only
+               a += wnorm2(v);
+             });
   double s = red_block(a, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// dots (basis_j, v) for j < k: partial[(2j) G + b] = Re, [(2j+1) G + b] = Im
-template <class VT>
-__global__ __launch_bounds__(QXD_BLOCK) void k_mdot(Ptrs basis, int k, const VT* __restrict__ v, size_t n,
+// The multi-vector kernels below are instantiated for every basis size K (0 ..
+// QXD_MAXKV): with the count fixed at compile time all loads of an element
+// (in groups of QXD_KGROUP) are issued before the first one is used, where a
+// run-time count left the compiler waiting for each load in turn.  The
+// arithmetic and its order are those of a plain loop over j.
+#define QXD_KGROUP 16
+
+// dots (basis_j, v) for j < K: partial[(2j) G + b] = Re, [(2j+1) G + b] = Im
+template <class VT, int K>
+__global__ __launch_bounds__(QXD_BLOCK) void k_mdot(Ptrs basis, const VT* __restrict__ v, size_t n,
                                                     double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
-  double re[QXD_MAXKV], im[QXD_MAXKV];
+  double re[K > 0 ? K : 1], im[K > 0 ? K : 1];
 #pragma unroll
-  for (int j = 0; j < QXD_MAXKV; ++j) re[j] = im[j] = 0.0;
+  for (int j = 0; j < K; ++j) re[j] = im[j] = 0.0;
   GRID_STRIDE(i, n) {
     VT vi = ld_stream(&v[i]);
 #pragma unroll
-    for (int j = 0; j < QXD_MAXKV; ++j)
-      if (j < k) wcdot(ld_stream(&((const VT*)basis.p[j])[i]), vi, re[j], im[j]);
+    for (int j0 = 0; j0 < K; j0 += QXD_KGROUP) {
+      VT bj[QXD_KGROUP];
+#pragma unroll
+      for (int j = 0; j < QXD_KGROUP; ++j)
+        if (j0 + j < K) bj[j] = ld_stream(&((const VT*)basis.p[j0 + j])[i]);
+#pragma unroll
+      for (int j = 0; j < QXD_KGROUP; ++j)
+        if (j0 + j < K) wcdot(bj[j], vi, re[j0 + j], im[j0 + j]);
+    }
   }
 #pragma unroll
-  for (int j = 0; j < QXD_MAXKV; ++j) {
-    if (j < k) {
-      double s = red_block(re[j], sh);
-      if (threadIdx.x == 0) partial[(size_t)(2 * j) * gridDim.x + blockIdx.x] = s;
-      s = red_block(im[j], sh);
-      if (threadIdx.x == 0) partial[(size_t)(2 * j + 1) * gridDim.x + blockIdx.x] = s;
-    }
+  for (int j = 0; j < K; ++j) {
+    double s = red_block(re[j], sh);
+    if (threadIdx.x == 0) partial[(size_t)(2 * j) * gridDim.x + blockIdx.x] = s;
+    s = red_block(im[j], sh);
+    if (threadIdx.x == 0) partial[(size_t)(2 * j + 1) * gridDim.x + blockIdx.x] = s;
   }
 }
 
-// v -= sum_j c_j basis_j (c complex at coef[2j], coef[2j+1]); partial |v|^2
-template <class VT>
-__global__ __launch_bounds__(QXD_BLOCK) void k_mupdate(VT* __restrict__ v, Ptrs basis, int k,
+// v -= sum_{j < K} c_j basis_j (c complex at coef[2j], coef[2j+1]); partial |v|^2
+template <class VT, int K>
+__global__ __launch_bounds__(QXD_BLOCK) void k_mupdate(VT* __restrict__ v, Ptrs basis,
                                                        const double* __restrict__ coef, size_t n,
                                                        double* __restrict__ partial) {
   __shared__ double sh[QXD_BLOCK / 64];
   double a = 0.0;
   GRID_STRIDE(i, n) {
     VT vi = ld_stream(&v[i]);
-    for (int j = 0; j < k; ++j) vi = wcaxpy(vi, -coef[2 * j], -coef[2 * j + 1], ld_stream(&((const VT*)basis.p[j])[i]));
+#pragma unroll
+    for (int j0 = 0; j0 < K; j0 += QXD_KGROUP) {
+      VT bj[QXD_KGROUP];
+#pragma unroll
+      for (int j = 0; j < QXD_KGROUP; ++j)
+        if (j0 + j < K) bj[j] = ld_stream(&((const VT*)basis.p[j0 + j])[i]);
+#pragma unroll
+      for (int j = 0; j < QXD_KGROUP; ++j)
+        if (j0 + j < K) vi = wcaxpy(vi, -coef[2 * (j0 + j)], -coef[2 * (j0 + j) + 1], bj[j]);
+    }
     st_stream(&v[i], vi);
     a += wnorm2(vi);
   }
@@ -188,11 +248,12 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_scale_cdot(VT* __restrict__ v, co
   const bool ok = n2 > 0.0 && n2 < INFINITY;
   const double sc = ok ? 1.0 / sqrt(n2) : 0.0;
   double re = 0.0, im = 0.0;
-  GRID_STRIDE(i, n) {
-    VT vi = ok ? wscale(ld_stream(&v[i]), sc) : VT{};
-    st_stream(&v[i], vi);
-    wcdot(vi, ld_stream(&r[i]), re, im);
-  }
+  stream_for(n, [&](size_t i) { return W2<VT>{ld_stream(&v[i]), ld_stream(&r[i])}; },
+             [&](size_t i, W2<VT> w) {
+               VT vi = ok ? wscale(w.a, sc) : VT{};
+               st_stream(&v[i], vi);
+               wcdot(vi, w.b, re, im);
+             });
   double s = red_block(re, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
   s = red_block(im, sh);
@@ -207,22 +268,32 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_r_update(VT* __restrict__ r, cons
   __shared__ double sh[QXD_BLOCK / 64];
   double cr = scal[i_c], ci = scal[i_c + 1];
   double a = 0.0;
-  GRID_STRIDE(i, n) {
-    VT ri = wcaxpy(ld_stream(&r[i]), -cr, -ci, ld_stream(&v[i]));
-    st_stream(&r[i], ri);
-    a += wnorm2(ri);
-  }
+  stream_for(n, [&](size_t i) { return W2<VT>{ld_stream(&r[i]), ld_stream(&v[i])}; },
+             [&](size_t i, W2<VT> w) {
+               VT ri = wcaxpy(w.a, -cr, -ci, w.b);
+               st_stream(&r[i], ri);
+               a += wnorm2(ri);
+             });
   double s = red_block(a, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// x += sum_j c_j basis_j
-template <class VT>
-__global__ __launch_bounds__(QXD_BLOCK) void k_multi_axpy(VT* __restrict__ x, Ptrs basis, int k,
+// x += sum_{j < K} c_j basis_j
+template <class VT, int K>
+__global__ __launch_bounds__(QXD_BLOCK) void k_multi_axpy(VT* __restrict__ x, Ptrs basis,
                                                           const double* __restrict__ coef, size_t n) {
   GRID_STRIDE(i, n) {
     VT xi = ld_stream(&x[i]);
-    for (int j = 0; j < k; ++j) xi = wcaxpy(xi, coef[2 * j], coef[2 * j + 1], ld_stream(&((const VT*)basis.p[j])[i]));
+#pragma unroll
+    for (int j0 = 0; j0 < K; j0 += QXD_KGROUP) {
+      VT bj[QXD_KGROUP];
+#pragma unroll
+      for (int j = 0; j < QXD_KGROUP; ++j)
+        if (j0 + j < K) bj[j] = ld_stream(&((const VT*)basis.p[j0 + j])[i]);
+#pragma unroll
+      for (int j = 0; j < QXD_KGROUP; ++j)
+        if (j0 + j < K) xi = wcaxpy(xi, coef[2 * (j0 + j)], coef[2 * (j0 + j) + 1], bj[j]);
+    }
     st_stream(&x[i], xi);
   }
 }
@@ -238,24 +309,38 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_zero(VT* __restrict__ x, size_t n
 __global__ __launch_bounds__(QXD_BLOCK) void k_down(float4* __restrict__ d, const double2* __restrict__ s, size_t Ve,
                                                     const double* __restrict__ scal, int i_n2) {
   double sc = 1.0 / sqrt(scal[i_n2]);
-  GRID_STRIDE(i, 6 * Ve) {
-    size_t j = i / Ve, h = i - j * Ve;
-    double2 a = s[(2 * j) * Ve + h], b = s[(2 * j + 1) * Ve + h];
-    d[i] = make_float4((float)(sc * a.x), (float)(sc * a.y), (float)(sc * b.x), (float)(sc * b.y));
-  }
+  stream_for(
+      6 * Ve,
+      [&](size_t i) {
+        size_t j = i / Ve, h = i - j * Ve;
+        return W2<double2>{s[(2 * j) * Ve + h], s[(2 * j + 1) * Ve + h]};
+      },
+      [&](size_t i, W2<double2> w) {
+        d[i] = make_float4((float)(sc * w.a.x), (float)(sc * w.a.y), (float)(sc * w.b.x), (float)(sc * w.b.y));
+      });
 }
 
 // x (FP64) += sqrt(scal[i]) e (FP32), same component map as k_down
 __global__ __launch_bounds__(QXD_BLOCK) void k_up_acc(double2* __restrict__ x, const float4* __restrict__ e, size_t Ve,
                                                       const double* __restrict__ scal, int i_n2) {
   double sc = sqrt(scal[i_n2]);
-  GRID_STRIDE(i, 6 * Ve) {
-    size_t j = i / Ve, h = i - j * Ve;
-    float4 v = e[i];
-    double2 a = x[(2 * j) * Ve + h], b = x[(2 * j + 1) * Ve + h];
-    x[(2 * j) * Ve + h] = make_double2(a.x + sc * (double)v.x, a.y + sc * (double)v.y);
-    x[(2 * j + 1) * Ve + h] = make_double2(b.x + sc * (double)v.z, b.y + sc * (double)v.w);
-  }
+  // the elements of a round touch distinct words of x, so their loads may all
+  // precede the stores
+  struct W3 {
+    float4 v;
+    double2 a, b;
+  };
+  stream_for(
+      6 * Ve,
+      [&](size_t i) {
+        size_t j = i / Ve, h = i - j * Ve;
+        return W3{e[i], x[(2 * j) * Ve + h], x[(2 * j + 1) * Ve + h]};
+      },
+      [&](size_t i, W3 w) {
+        size_t j = i / Ve, h = i - j * Ve;
+        x[(2 * j) * Ve + h] = make_double2(w.a.x + sc * (double)w.v.x, w.a.y + sc * (double)w.v.y);
+        x[(2 * j + 1) * Ve + h] = make_double2(w.b.x + sc * (double)w.v.z, w.b.y + sc * (double)w.v.w);
+      });
 }
 
 // ---- host launchers -------------------------------------------------------
@@ -290,15 +375,38 @@ void blas_sub_norm(qxd_handle* h, VT* r, const VT* b, const VT* w, size_t n, dou
   hipLaunchKernelGGL(k_sub_norm<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, r, b, w, n, h->partial);
   launch_final_sum(h->partial, QXD_NRED, 1, QXD_NRED, slot, s);
 }
+// one case per basis size 0 .. QXD_MAXKV
+#define QXD_K_CASES(X)                                                                                         \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+  X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+static_assert(QXD_MAXKV == 32, "QXD_K_CASES lists the basis sizes 0 .. QXD_MAXKV");
+
 template <class VT>
 void blas_mdot(qxd_handle* h, const Ptrs& basis, int k, const VT* v, size_t n, double* slots, hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, basis, k, v, n, h->partial);
+  switch (k) {
+#define QXD_CASE(K)                                                                                             \
+  case K:                                                                                                     \
+    hipLaunchKernelGGL((k_mdot<VT, K>), dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, basis, v, n, h->partial);      \
+    break;
+    QXD_K_CASES(QXD_CASE)
+#undef QXD_CASE
+    default: return;  // callers keep 0 <= k <= QXD_MAXKV
+  }
   launch_final_sum(h->partial, QXD_NRED, 2 * k, QXD_NRED, slots, s);
 }
 template <class VT>
 void blas_mupdate(qxd_handle* h, VT* v, const Ptrs& basis, int k, const double* coef, size_t n, double* slot,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_mupdate<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, v, basis, k, coef, n, h->partial);
+  switch (k) {
+#define QXD_CASE(K)                                                                                             \
+  case K:                                                                                                     \
+    hipLaunchKernelGGL((k_mupdate<VT, K>), dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, v, basis, coef, n,           \
+                       h->partial);                                                                           \
+    break;
+    QXD_K_CASES(QXD_CASE)
+#undef QXD_CASE
+    default: return;
+  }
   launch_final_sum(h->partial, QXD_NRED, 1, QXD_NRED, slot, s);
 }
 template <class VT>
@@ -313,7 +421,15 @@ void blas_r_update(qxd_handle* h, VT* r, const VT* v, size_t n, int i_c, double*
 }
 template <class VT>
 void blas_multi_axpy(qxd_handle* h, VT* x, const Ptrs& basis, int k, const double* coef, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_multi_axpy<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, basis, k, coef, n);
+  switch (k) {
+#define QXD_CASE(K)                                                                                             \
+  case K:                                                                                                     \
+    hipLaunchKernelGGL((k_multi_axpy<VT, K>), dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, x, basis, coef, n);      \
+    break;
+    QXD_K_CASES(QXD_CASE)
+#undef QXD_CASE
+    default: return;
+  }
 }
 template <class VT>
 void blas_zero(VT* x, size_t n, hipStream_t s) {

@@ -262,6 +262,12 @@ qxd_status fgcr(qxd_handle* h, InnerOp op, Precond pc, int fallback_after, VT* x
   return QXD_OK;
 }
 
+// Default reduction of an inner solve: 1e-5 with the FP32 operator; 1e-3 with
+// bfloat16 links and spinors, whose operator differs from the FP64 one by a
+// few 1e-3, so that solving it further buys no outer progress (measured: fewer
+// inner iterations in total at 64 x 32^3 for CG and FGCR).
+double default_inner_res(int inner_prec) { return inner_prec == QXD_BF16 ? 1e-3 : 1e-5; }
+
 qxd_status check_params(const qxd_solver_params* p) {
   if (!p) return QXD_EINVAL;
   if (p->nmx < 1 || !(p->res > 0.0)) return QXD_EINVAL;
@@ -295,7 +301,7 @@ qxd_status solve_cg_dc(qxd_handle* h, const qxd_solver_params* prm, void* x, con
   QXD_TRY(read_scal(h, S_RR, 1, s));
   double rr = h->scal_host[S_RR];
   const int max_outer = prm->max_outer > 0 ? prm->max_outer : 100;
-  const double inner_res = prm->inner_res > 0 ? prm->inner_res : 1e-5;
+  const double inner_res = prm->inner_res > 0 ? prm->inner_res : default_inner_res(prm->inner_prec);
   const int check = prm->check_every > 0 ? prm->check_every : 1;
   int steps_left = prm->nmx;
   InnerOp op{prm->inner_prec == QXD_F32 ? 1 : 2};
@@ -460,7 +466,7 @@ qxd_status solve_fgcr(qxd_handle* h, const qxd_solver_params* prm, qxd_nn* net, 
   QXD_TRY(read_scal(h, S_RR, 1, s));
   double rr = h->scal_host[S_RR];
   int max_outer = prm->max_outer > 0 ? prm->max_outer : 100;
-  double inner_res = prm->inner_res > 0 ? prm->inner_res : 1e-5;
+  double inner_res = prm->inner_res > 0 ? prm->inner_res : default_inner_res(prm->inner_prec);
   int fallback_after = prm->fallback_after > 0 ? prm->fallback_after : 50;
   int steps_left = prm->nmx;
   rc = QXD_ENOCONV;
