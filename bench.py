@@ -601,9 +601,9 @@ def solve_leg(qxd, torch, lats, w, flavours, nets, big=False, only=(), b=None):
     preconditioned by the flavour's network (`nets`, trained on 32 x 16^3
     fields with the same statistics; the network is local, so its weights
     apply on any lattice).  `big` (the 128 x 64^3 lattice): one timed solve per
-    leg, no SAP legs, the CG workspaces released before FGCR, and FGCR with the
-    largest restart length of 12, 10, ..., 4 whose directions fit beside the
-    operator."""
+    leg, only the tuned SAP setting, every workspace released before each FGCR
+    leg, and each FGCR leg with the largest restart length of 12, 10, ..., 4
+    whose directions fit beside the operator (and the SAP block copies)."""
     import synthgen as sg
     from paper_1908_11673_amd import learned
     out = {}
@@ -634,13 +634,13 @@ def solve_leg(qxd, torch, lats, w, flavours, nets, big=False, only=(), b=None):
 
         legs = [("cg_f64", cg(qxd.F64)), ("cg_f32_in_f64", cg(qxd.F32)), ("cg_bf16links_in_f64", cg(qxd.BF16))]
         legs.append(("fgcr_f32_in_f64", (qxd.F32, None)))
-        if not big:  # the SAP block copies do not fit beside the 128 x 64^3 operator and FGCR's directions
-            legs += [("fgcr_bf16links_in_f64", (qxd.BF16, None)),
-                     ("fgcr_f32_sap_in_f64", (qxd.F32, None, SAP_NCY, SAP_NMR, SAP_PLAIN)),
-                     ("fgcr_f32_sap_eo55_in_f64", (qxd.F32, None, 5, 5, 0))]
+        if not big:
+            legs.append(("fgcr_bf16links_in_f64", (qxd.BF16, None)))
+        legs.append(("fgcr_f32_sap_in_f64", (qxd.F32, None, SAP_NCY, SAP_NMR, SAP_PLAIN)))
+        if not big:
+            legs.append(("fgcr_f32_sap_eo55_in_f64", (qxd.F32, None, 5, 5, 0)))
         if net is not None:
             legs.append(("fgcr_f32_nn_in_f64", (qxd.F32, net)))
-        trimmed = False
         for tag, fn in legs:
             if only and tag not in only:
                 continue
@@ -648,10 +648,10 @@ def solve_leg(qxd, torch, lats, w, flavours, nets, big=False, only=(), b=None):
                 spec = fn
                 fn = fgcr(*spec)
                 if big:
-                    if not trimmed:  # drop the CG legs' workspaces before FGCR allocates its own
-                        qxd.qxd_trim(lat.h)
-                        torch.cuda.empty_cache()
-                        trimmed = True
+                    # drop the previous legs' workspaces and copies before this one allocates its own
+                    qxd.qxd_trim(lat.h)
+                    torch.cuda.empty_cache()
+                    nkv[0] = 12
                     # untimed one-step call: allocates the 2 nkv directions (fewer if they do not fit)
                     while fgcr(*spec, nmx=1)()["status"] == 3 and nkv[0] > 4:
                         qxd.qxd_trim(lat.h)
@@ -679,8 +679,8 @@ def solve_leg(qxd, torch, lats, w, flavours, nets, big=False, only=(), b=None):
     return out
 
 
-C4_LEGS = {"qhat-2": ("cg_f64", "cg_f32_in_f64", "fgcr_f32_in_f64", "fgcr_f32_nn_in_f64"),
-           "qhat+4": ("cg_f64", "cg_f32_in_f64")}
+C4_LEGS = {"qhat-2": ("cg_f64", "cg_f32_in_f64", "fgcr_f32_in_f64", "fgcr_f32_sap_in_f64", "fgcr_f32_nn_in_f64"),
+           "qhat+4": ("cg_f64", "fgcr_f32_sap_in_f64")}
 C4_BUDGET_S = 220.0  # bench seconds elapsed after which the up-type solves at 128 x 64^3 are left out
 
 
@@ -689,15 +689,15 @@ def c4_leg(qxd, torch, nets, t_start):
     128 x 64^3 physical lattice with C* in three directions (extended 128 x 128
     x 64 x 64, 67,108,864 sites), both flavours one after the other on one
     handle; one Gaussian source, one timed solve each.  Down-type: FP64 CG
-    against defect-correction CG (FP32 inner), FP32-inner FGCR and
-    network-preconditioned FP32-inner FGCR.  Up-type: FP64 CG against
-    defect-correction CG only; at this volume its operator needs about 1650 CG
-    iterations, FGCR with the restart lengths whose directions fit (12 and
-    less) stalls near 1e-6 after 2500 steps, and the network gains no steps for
-    this flavour at any volume measured.  The handle holds the FP64 operator
-    (97 GB) and only the lower-precision copies the running solve uses.  The
-    up-type solves are left out if the bench has already run C4_BUDGET_S
-    seconds (about 200 s of solves)."""
+    against defect-correction CG (FP32 inner), FP32-inner FGCR, SAP-preconditioned
+    FP32-inner FGCR and network-preconditioned FP32-inner FGCR.  Up-type: FP64
+    CG against SAP-preconditioned FGCR only; at this volume its operator needs
+    about 1650 CG iterations (defect-correction CG about 2830 inner ones, 94 s),
+    plain FGCR with the restart lengths whose directions fit (12 and less)
+    stalls near 1e-6 after 2500 steps, and the network gains no steps for this
+    flavour at any volume measured.  The handle holds the FP64 operator (97 GB)
+    and only the lower-precision copies the running solve uses.  The up-type
+    solves are left out if the bench has already run C4_BUDGET_S seconds."""
     import synthgen as sg
     w4 = sg.WORKLOADS["c4"]
     t0 = time.perf_counter()

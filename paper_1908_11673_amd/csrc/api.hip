@@ -69,8 +69,8 @@ extern "C" qxd_status qxd_create(const qxd_geom* g, qxd_handle** out) {
   }
   h->npartial = (size_t)QXD_MAX_PARTIAL;
   if ((size_t)div_up(h->Ve, 64) > h->npartial) h->npartial = (size_t)div_up(h->Ve, 64);
-  if (hipMalloc(&h->partial, h->npartial * sizeof(double)) != hipSuccess ||
-      hipMalloc(&h->scal, QXD_NSCAL * sizeof(double)) != hipSuccess ||
+  if (!dev_alloc(&h->partial, h->npartial * sizeof(double)) ||
+      !dev_alloc(&h->scal, QXD_NSCAL * sizeof(double)) ||
       hipHostMalloc(&h->scal_host, QXD_NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     release(h);
     delete h;
@@ -114,15 +114,19 @@ extern "C" qxd_status qxd_trim(qxd_handle* h) {
   return QXD_OK;
 }
 
-void release_copies(qxd_handle* h) {
-  void** ptrs[] = {reinterpret_cast<void**>(&h->V32), reinterpret_cast<void**>(&h->V16),
-                   reinterpret_cast<void**>(&h->He32), reinterpret_cast<void**>(&h->Ho32),
-                   reinterpret_cast<void**>(&h->Hi32)};
-  for (void** p : ptrs) {
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
+void release_copies(qxd_handle* h, unsigned which) {
+  const struct {
+    unsigned bit;
+    void** p;
+  } cp[] = {{CP_V32, reinterpret_cast<void**>(&h->V32)}, {CP_V16, reinterpret_cast<void**>(&h->V16)},
+            {CP_HE32, reinterpret_cast<void**>(&h->He32)}, {CP_HO32, reinterpret_cast<void**>(&h->Ho32)},
+            {CP_HI32, reinterpret_cast<void**>(&h->Hi32)}};
+  for (const auto& c : cp) {
+    if (!(which & c.bit)) continue;
+    if (*c.p) (void)hipFree(*c.p);
+    *c.p = nullptr;
+    h->copies &= ~c.bit;
   }
-  h->copies = 0;
 }
 
 extern "C" qxd_status qxd_volume(const qxd_handle* h, int64_t* V, int64_t* Ve) {

@@ -346,9 +346,13 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_clover_cast(int Ve, const double2
 static qxd_status alloc_clover(qxd_handle* h) {
   if (h->He64) return QXD_OK;
   size_t n64 = (size_t)36 * h->Ve * sizeof(double2);
-  if (hipMalloc(&h->He64, n64) != hipSuccess || hipMalloc(&h->Ho64, n64) != hipSuccess ||
-      hipMalloc(&h->Hi64, n64) != hipSuccess)
+  if (!dev_alloc(&h->He64, n64) || !dev_alloc(&h->Ho64, n64) || !dev_alloc(&h->Hi64, n64)) {
+    for (double2** p : {&h->He64, &h->Ho64, &h->Hi64}) {  // all or none, so that the next call allocates again
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
     return QXD_ENOMEM;
+  }
   return QXD_OK;
 }
 
@@ -369,7 +373,7 @@ qxd_status ensure_copies(qxd_handle* h, unsigned which, hipStream_t s) {
   for (auto& c : cl) {
     if (!(which & c.bit) || (h->copies & c.bit)) continue;
     if (!c.ready) return QXD_ESTATE;
-    if (!*c.dst && hipMalloc(c.dst, n32) != hipSuccess) return QXD_ENOMEM;
+    if (!*c.dst && !dev_alloc(c.dst, n32)) return QXD_ENOMEM;
     hipLaunchKernelGGL(k_clover_cast, dim3(g18), dim3(QXD_BLOCK), 0, s, (int)h->Ve, c.src, *c.dst);
     QXD_HIP(hipGetLastError());
     h->copies |= c.bit;

@@ -502,16 +502,16 @@ extern "C" qxd_status qxd_dfl_create(qxd_handle* h, int ns, qxd_dfl** out) {
   d->nblk = (g.Le0 / kSapB) * (g.Le1 / kSapB) * (g.Le2 / kSapB) * (g.Le3 / kSapB);
   d->sb = SapGeo{g.Le1 / kSapB, g.Le2 / kSapB, g.Le3 / kSapB, d->nblk / 2};
   const size_t V = (size_t)h->V, N = (size_t)d->nblk * ns;
-  bool ok = hipMalloc(&d->W, V * ns * 6 * sizeof(float4)) == hipSuccess &&
-            hipMalloc(&d->A, N * 9 * ns * sizeof(float2)) == hipSuccess &&
-            hipMalloc(&d->nbr, (size_t)d->nblk * 9 * sizeof(int)) == hipSuccess &&
-            hipMalloc(&d->cb, N * sizeof(float2)) == hipSuccess && hipMalloc(&d->cx, N * sizeof(float2)) == hipSuccess &&
-            hipMalloc(&d->cr, N * sizeof(float2)) == hipSuccess &&
-            hipMalloc(&d->cz, kDflMaxNc * N * sizeof(float2)) == hipSuccess &&
-            hipMalloc(&d->cw, kDflMaxNc * N * sizeof(float2)) == hipSuccess &&
-            hipMalloc(&d->psi, V * 6 * sizeof(float4)) == hipSuccess &&
-            hipMalloc(&d->t, V * 6 * sizeof(float4)) == hipSuccess &&
-            hipMalloc(&d->xs, V * 3 * sizeof(float4)) == hipSuccess;
+  bool ok = dev_alloc(&d->W, V * ns * 6 * sizeof(float4)) &&
+            dev_alloc(&d->A, N * 9 * ns * sizeof(float2)) &&
+            dev_alloc(&d->nbr, (size_t)d->nblk * 9 * sizeof(int)) &&
+            dev_alloc(&d->cb, N * sizeof(float2)) && dev_alloc(&d->cx, N * sizeof(float2)) &&
+            dev_alloc(&d->cr, N * sizeof(float2)) &&
+            dev_alloc(&d->cz, kDflMaxNc * N * sizeof(float2)) &&
+            dev_alloc(&d->cw, kDflMaxNc * N * sizeof(float2)) &&
+            dev_alloc(&d->psi, V * 6 * sizeof(float4)) &&
+            dev_alloc(&d->t, V * 6 * sizeof(float4)) &&
+            dev_alloc(&d->xs, V * 3 * sizeof(float4));
   if (!ok) {
     qxd_dfl_destroy(d);
     return QXD_ENOMEM;

@@ -182,7 +182,7 @@ static size_t half_bytes(const qxd_handle* h, qxd_prec p) { return (size_t)group
 
 static qxd_status ensure_t(qxd_handle* h, qxd_prec p) {
   void** t = p == QXD_F64 ? (void**)&h->t64 : p == QXD_F32 ? (void**)&h->t32 : (void**)&h->t16;
-  if (!*t && hipMalloc(t, half_bytes(h, p)) != hipSuccess) return QXD_ENOMEM;
+  if (!*t && !dev_alloc(t, half_bytes(h, p))) return QXD_ENOMEM;
   return QXD_OK;
 }
 

@@ -66,14 +66,14 @@ qxd_status ensure_link_copies(qxd_handle* h, unsigned which, hipStream_t s) {
   const int64_t n = (int64_t)2 * 4 * 9 * h->Ve;
   if ((which & CP_V32) && !(h->copies & CP_V32)) {
     if (!h->has_flavour) return QXD_ESTATE;
-    if (!h->V32 && hipMalloc(&h->V32, n * sizeof(float2)) != hipSuccess) return QXD_ENOMEM;
+    if (!h->V32 && !dev_alloc(&h->V32, n * sizeof(float2))) return QXD_ENOMEM;
     hipLaunchKernelGGL(k_link_cast32, dim3(div_up(n, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, n, h->V64, h->V32);
     QXD_HIP(hipGetLastError());
     h->copies |= CP_V32;
   }
   if ((which & CP_V16) && !(h->copies & CP_V16)) {
     if (!h->has_flavour) return QXD_ESTATE;
-    if (!h->V16 && hipMalloc(&h->V16, n * sizeof(uint32_t)) != hipSuccess) return QXD_ENOMEM;
+    if (!h->V16 && !dev_alloc(&h->V16, n * sizeof(uint32_t))) return QXD_ENOMEM;
     hipLaunchKernelGGL(k_link_cast16, dim3(div_up(n, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, n, h->V64, h->V16);
     QXD_HIP(hipGetLastError());
     h->copies |= CP_V16;
@@ -88,8 +88,12 @@ extern "C" qxd_status qxd_set_gauge(qxd_handle* h, const double* U_phys, const d
   size_t nU = (size_t)4 * h->Vphys * 18 * sizeof(double);
   size_t nA = (size_t)4 * h->Vphys * sizeof(double);
   if (!h->Uphys) {
-    if (hipMalloc(&h->Uphys, nU) != hipSuccess) return QXD_ENOMEM;
-    if (hipMalloc(&h->Aphys, nA) != hipSuccess) return QXD_ENOMEM;
+    if (!dev_alloc(&h->Uphys, nU)) return QXD_ENOMEM;
+    if (!dev_alloc(&h->Aphys, nA)) {
+      (void)hipFree(h->Uphys);  // both or neither
+      h->Uphys = nullptr;
+      return QXD_ENOMEM;
+    }
   }
   if (on_device) {
     QXD_HIP(hipMemcpyAsync(h->Uphys, U_phys, nU, hipMemcpyDeviceToDevice, s));
@@ -110,7 +114,7 @@ extern "C" qxd_status qxd_set_flavour(qxd_handle* h, const qxd_flavour* f, void*
   if (!(f->kappa > 0.0) || !(f->invqel > 0.0)) return QXD_EINVAL;
   hipStream_t s = as_stream(stream);
   size_t nl = (size_t)2 * 4 * 9 * h->Ve;
-  if (!h->V64 && hipMalloc(&h->V64, nl * sizeof(double2)) != hipSuccess) return QXD_ENOMEM;
+  if (!h->V64 && !dev_alloc(&h->V64, nl * sizeof(double2))) return QXD_ENOMEM;
   h->copies = 0;
   PhysExt pe;
   for (int m = 0; m < 4; ++m) pe.L[m] = h->g.L[m];

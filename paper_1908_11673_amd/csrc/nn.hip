@@ -785,12 +785,22 @@ static bool nn_blocks_fit(const Geo& g) {
   return g.Le0 % NnBlock::B0 == 0 && g.Le1 % NnBlock::B1 == 0 && g.Le2 % NnBlock::B2 == 0 && g.Le3 % NnBlock::B3 == 0;
 }
 
+// free the buffers at ptrs and null them (a partly failed allocation leaves
+// nothing behind, so that the next call allocates again)
+static void nn_free_all(std::initializer_list<void**> ptrs) {
+  for (void** p : ptrs) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+}
+
 static qxd_status nn_alloc_act(qxd_nn* net) {
   if (net->a0) return QXD_OK;
   size_t bytes = (size_t)net->h->V * NN_C * sizeof(uint16_t);
-  if (hipMalloc(&net->a0, bytes) != hipSuccess || hipMalloc(&net->a1, bytes) != hipSuccess ||
-      hipMalloc(&net->a2, bytes) != hipSuccess)
+  if (!dev_alloc(&net->a0, bytes) || !dev_alloc(&net->a1, bytes) || !dev_alloc(&net->a2, bytes)) {
+    nn_free_all({(void**)&net->a0, (void**)&net->a1, (void**)&net->a2});
     return QXD_ENOMEM;
+  }
   return QXD_OK;
 }
 
@@ -800,13 +810,15 @@ static qxd_status nn_alloc_train(qxd_nn* net, hipStream_t s) {
   qxd_handle* h = net->h;
   size_t bytes = (size_t)h->V * NN_C * sizeof(uint16_t);
   net->nchunk = div_up(h->V, kWgChunk);
-  if (hipMalloc(&net->g3, bytes) != hipSuccess || hipMalloc(&net->gA, bytes) != hipSuccess ||
-      hipMalloc(&net->gB, bytes) != hipSuccess ||
-      hipMalloc(&net->y, (size_t)h->Ve * 24 * sizeof(float)) != hipSuccess ||
-      hipMalloc(&net->dv, (size_t)h->Ve * 24 * sizeof(float)) != hipSuccess ||
-      hipMalloc(&net->dz, (size_t)h->Ve * 24 * sizeof(float)) != hipSuccess ||
-      hipMalloc(&net->part, (size_t)net->nchunk * NN_TAPS * NN_C * NN_C * sizeof(float)) != hipSuccess)
+  if (!dev_alloc(&net->g3, bytes) || !dev_alloc(&net->gA, bytes) || !dev_alloc(&net->gB, bytes) ||
+      !dev_alloc(&net->y, (size_t)h->Ve * 24 * sizeof(float)) ||
+      !dev_alloc(&net->dv, (size_t)h->Ve * 24 * sizeof(float)) ||
+      !dev_alloc(&net->dz, (size_t)h->Ve * 24 * sizeof(float)) ||
+      !dev_alloc(&net->part, (size_t)net->nchunk * NN_TAPS * NN_C * NN_C * sizeof(float))) {
+    nn_free_all({(void**)&net->g3, (void**)&net->gA, (void**)&net->gB, (void**)&net->y, (void**)&net->dv,
+                 (void**)&net->dz, (void**)&net->part});
     return QXD_ENOMEM;
+  }
   // the odd half of g3 is never written: zero once
   QXD_HIP(hipMemsetAsync(net->g3, 0, bytes, s));
   return QXD_OK;
@@ -909,10 +921,10 @@ extern "C" qxd_status qxd_nn_create(qxd_handle* h, qxd_nn** out) {
       hipDeviceGetAttribute(&net->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || net->ncu < 1)
     net->ncu = 1;
   size_t n = QXD_NN_NWEIGHTS;
-  if (hipMalloc(&net->w, n * 4) != hipSuccess || hipMalloc(&net->m, n * 4) != hipSuccess ||
-      hipMalloc(&net->v, n * 4) != hipSuccess || hipMalloc(&net->grad, n * 4) != hipSuccess ||
-      hipMalloc(&net->wf, (size_t)3 * NN_LAYER_W * 2) != hipSuccess ||
-      hipMalloc(&net->wa, (size_t)3 * NN_LAYER_W * 2) != hipSuccess) {
+  if (!dev_alloc(&net->w, n * 4) || !dev_alloc(&net->m, n * 4) ||
+      !dev_alloc(&net->v, n * 4) || !dev_alloc(&net->grad, n * 4) ||
+      !dev_alloc(&net->wf, (size_t)3 * NN_LAYER_W * 2) ||
+      !dev_alloc(&net->wa, (size_t)3 * NN_LAYER_W * 2)) {
     qxd_nn_destroy(net);
     return QXD_ENOMEM;
   }

@@ -388,13 +388,24 @@ enum {
 };
 #define QXD_MAXKV_R 32
 
+// hipMalloc that leaves no error behind when it fails: the caller reports
+// QXD_ENOMEM, and the launch checks of later calls must not see the failed
+// allocation again as a HIP error.
+template <class T>
+inline bool dev_alloc(T** p, size_t bytes) {
+  if (hipMalloc(reinterpret_cast<void**>(p), bytes) == hipSuccess) return true;
+  *p = nullptr;
+  (void)hipGetLastError();
+  return false;
+}
+
 // grow-only device workspace number i of at least `bytes`
 inline void* ws_get(qxd_handle* h, int i, size_t bytes) {
   if (h->ws_bytes[i] >= bytes) return h->ws[i];
   if (h->ws[i]) (void)hipFree(h->ws[i]);
   h->ws[i] = nullptr;
   h->ws_bytes[i] = 0;
-  if (hipMalloc(&h->ws[i], bytes) != hipSuccess) return nullptr;
+  if (!dev_alloc(&h->ws[i], bytes)) return nullptr;
   h->ws_bytes[i] = bytes;
   return h->ws[i];
 }
@@ -437,10 +448,12 @@ qxd_status sap_apply_internal(qxd_handle* h, int ncy, int nmr, int eo, float4* o
 // blocks H_e, H_o, H_o^-1 in FP32) are made from the FP64 ones when a call
 // first needs them and released by qxd_trim, so that a handle holds only the
 // copies the computations it runs use.  ensure_copies makes the `which` copies
-// current (QXD_ESTATE if their FP64 source is not set up, QXD_ENOMEM).
-enum : unsigned { CP_V32 = 1u, CP_V16 = 2u, CP_HE32 = 4u, CP_HO32 = 8u, CP_HI32 = 16u };
+// current (QXD_ESTATE if their FP64 source is not set up, QXD_ENOMEM);
+// release_copies frees the `which` copies (the caller makes sure no queued
+// work still reads them).
+enum : unsigned { CP_V32 = 1u, CP_V16 = 2u, CP_HE32 = 4u, CP_HO32 = 8u, CP_HI32 = 16u, CP_ALL = 31u };
 qxd_status ensure_copies(qxd_handle* h, unsigned which, hipStream_t s);
-void release_copies(qxd_handle* h);
+void release_copies(qxd_handle* h, unsigned which = CP_ALL);
 
 // device address of the static workspace of qxd_dw_eo_schur_noalloc on
 // `device` (the current device), looked up once per device (dirac.hip)

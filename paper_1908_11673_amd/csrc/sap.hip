@@ -378,11 +378,16 @@ namespace {
 
 // The block-order copies of links and clover blocks for slot order eo (made
 // when the links, the clover blocks or the slot order changed since the last).
+// The inverse blocks on odd sites are copied for the even-odd block solver
+// only: the plain one never reads CIb, which then aliases Cb.  The FP32 odd
+// clover blocks are cast for the copy and released after it if no other call
+// had them, since the block copy holds them from then on (at 128 x 64^3 they
+// are 9.7 GB).
 qxd_status sap_pack(qxd_handle* h, int eo, float2** Vb, float4** Cb, float4** CIb, SapGeo* sb, hipStream_t s) {
   const size_t V = (size_t)h->V;
   *Vb = (float2*)ws_get(h, W_SAP_VB, V * 36 * sizeof(float2));
   *Cb = (float4*)ws_get(h, W_SAP_CB, V * 18 * sizeof(float4));
-  *CIb = (float4*)ws_get(h, W_SAP_CIB, V / 2 * 18 * sizeof(float4));
+  *CIb = eo ? (float4*)ws_get(h, W_SAP_CIB, V / 2 * 18 * sizeof(float4)) : *Cb;
   if (!*Vb || !*Cb || !*CIb) return QXD_ENOMEM;
   const Geo& g = h->geo;
   const int nblk = (g.Le0 / kSapB) * (g.Le1 / kSapB) * (g.Le2 / kSapB) * (g.Le3 / kSapB);
@@ -390,12 +395,17 @@ qxd_status sap_pack(qxd_handle* h, int eo, float2** Vb, float4** Cb, float4** CI
   // the copies are tagged 2 setup_gen + eo
   const uint64_t tag = 2 * h->setup_gen + (uint64_t)eo;
   if (h->sap_gen != tag) {
-    QXD_TRY(ensure_copies(h, CP_V32 | CP_HE32 | CP_HO32 | CP_HI32, s));
+    const bool had_ho = (h->copies & CP_HO32) != 0;
+    QXD_TRY(ensure_copies(h, CP_V32 | CP_HE32 | CP_HO32 | (eo ? CP_HI32 : 0u), s));
     auto pack = eo ? k_sap_pack<true> : k_sap_pack<false>;
     hipLaunchKernelGGL(pack, dim3(nblk), dim3(kSapSites), 0, s, g, *sb, reinterpret_cast<const float2*>(h->V32),
                        reinterpret_cast<const float4*>(h->He32), reinterpret_cast<const float4*>(h->Ho32),
-                       reinterpret_cast<const float4*>(h->Hi32), *Vb, *Cb, *CIb);
+                       reinterpret_cast<const float4*>(eo ? h->Hi32 : h->Ho32), *Vb, *Cb, *CIb);
     QXD_HIP(hipGetLastError());
+    if (!had_ho) {
+      QXD_HIP(hipStreamSynchronize(s));
+      release_copies(h, CP_HO32);
+    }
     h->sap_gen = tag;
   }
   return QXD_OK;

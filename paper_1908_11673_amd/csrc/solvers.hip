@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "blas.hpp"
+#include "sap_blocks.hpp"
 
 namespace {
 
@@ -441,6 +442,14 @@ qxd_status solve_fgcr(qxd_handle* h, const qxd_solver_params* prm, qxd_nn* net, 
   }
   if (mode == 0 && pc.any()) return QXD_EINVAL;  // the preconditioners run on FP32 vectors
   hipStream_t s = as_stream(stream);
+  if (pc.sap_ncy > 0 && !dfl) {
+    // the SAP block copies first, while the FP32 odd clover blocks they are
+    // made from need not share the memory with the solver's vectors
+    const float2* vb;
+    const float4* cb;
+    SapGeo sb;
+    QXD_TRY(sap_blocks(h, pc.sap_eo, &vb, &cb, &sb, s));
+  }
   size_t n64 = (size_t)12 * h->Ve, n32 = (size_t)6 * h->Ve;
   size_t b64 = n64 * sizeof(double2);
   double2 *bh = (double2*)ws_get(h, W_BH, b64), *xe = (double2*)ws_get(h, W_XE, b64);
@@ -573,7 +582,7 @@ extern "C" qxd_status qxd_nn_harvest(qxd_handle* h, const void* b, int npairs, v
     if (std::sqrt(h->scal_host[S_FRR]) < rec_floor) return QXD_OK;
     if (cycle++ % stride != 0) return QXD_OK;
     double2 *xs = nullptr, *rs = nullptr;
-    if (hipMalloc(&xs, b64) != hipSuccess || hipMalloc(&rs, b64) != hipSuccess) {
+    if (!dev_alloc(&xs, b64) || !dev_alloc(&rs, b64)) {
       if (xs) (void)hipFree(xs);
       cb_status = QXD_ENOMEM;
       return QXD_ENOMEM;

@@ -4,9 +4,10 @@ operator takes 97 GB of the GPU, the FP32 copies another 48 GB when used), both
 flavours.  The Schur operator in the launch configuration the benchmark times
 at this size (windows of 16 tiles per XCD), checked against the oracle on
 sampled even sites, including the lattice corners where every C* crossing
-happens (FP64 to 1e-13, FP32 to 1e-6); and a mixed-precision solve checked by
-the oracle's residual on sampled sites (the up-type flavour needs about 2830
-inner CG iterations here, about 95 s)."""
+happens (FP64 to 1e-13, FP32 to 1e-6); and a mixed-precision CG solve and a
+SAP-preconditioned mixed-precision FGCR solve, each checked by the oracle's
+residual on sampled sites (the up-type flavour needs about 2830 inner CG
+iterations here, about 95 s)."""
 import numpy as np
 import pytest
 
@@ -88,6 +89,24 @@ def test_schur_f32_max_size_sampled(biggest):
     assert err < 1e-6
 
 
+def _oracle_residual(o, lat, x, b, seed):
+    """The oracle's relative residual |b - D x| on sampled even and odd sites
+    (including the corners), after qxd_trim made room for the unpacked x."""
+    qxd.qxd_trim(lat.h)  # the solver's workspaces, before the unpacked solution takes their room
+    torch.cuda.empty_cache()
+    odd = np.nonzero(o.parity() == 1)[0]
+    sites = np.concatenate([_sample(o, seed=seed), np.random.default_rng(seed + 1).choice(odd, 64, replace=False)])
+    xs = lat.unpack(x)
+    xh = np.zeros((o.V, 4, 3), dtype=np.complex128)
+    need = np.unique(np.concatenate([sites, o.neighbours()[0][sites].reshape(-1)]))
+    xh[need] = xs[torch.from_numpy(need).cuda()].cpu().numpy()
+    del xs
+    torch.cuda.empty_cache()
+    res = np.linalg.norm(b[sites] - o.dirac_sites(xh, sites)) / np.linalg.norm(b[sites])
+    print("oracle residual on %d sampled sites: %.2e" % (sites.size, res))
+    return res
+
+
 def test_mixed_precision_cg_solves_at_max_size(biggest):
     """Defect-correction CG (FP32 inner, FP64 outer) at the largest share, after
     qxd_trim drops the gauge copy: the FP64 true residual 1e-10, and the
@@ -104,17 +123,30 @@ def test_mixed_precision_cg_solves_at_max_size(biggest):
     print("max-size defect-correction CG: %d iterations, true residual %.2e" % (st["inner_it"], st["true_residual"]))
     assert st["status"] == 0 and st["true_residual"] <= 1e-10
     del bd
-    qxd.qxd_trim(lat.h)  # the solver's workspaces, before the unpacked solution takes their room
+    assert _oracle_residual(o, lat, x, b, 2) <= 1e-9
+
+
+def test_sap_fgcr_solves_at_max_size(biggest):
+    """SAP-preconditioned FGCR (FP32 inner with 2 SAP cycles of 8 plain
+    minimal-residual steps, FP64 defect correction) at the largest share: the
+    block-order copies fit beside the FP64 operator with restart length 6 (4 if
+    6 does not fit); the FP64 true residual 1e-10 and the oracle's residual on
+    sampled sites; the step limit bounds the run."""
+    o, lat, _ = biggest
+    qxd.qxd_trim(lat.h)
     torch.cuda.empty_cache()
-    odd = np.nonzero(o.parity() == 1)[0]
-    sites = np.concatenate([_sample(o, seed=2), np.random.default_rng(3).choice(odd, 64, replace=False)])
-    xs = lat.unpack(x)
-    del x
-    xh = np.zeros((o.V, 4, 3), dtype=np.complex128)
-    need = np.unique(np.concatenate([sites, o.neighbours()[0][sites].reshape(-1)]))
-    xh[need] = xs[torch.from_numpy(need).cuda()].cpu().numpy()
-    del xs
-    torch.cuda.empty_cache()
-    res = np.linalg.norm(b[sites] - o.dirac_sites(xh, sites)) / np.linalg.norm(b[sites])
-    print("oracle residual on %d sampled sites: %.2e" % (sites.size, res))
-    assert res <= 1e-9
+    b = sg.spinor(W["source_seed"] + 2, o.V)
+    bd = lat.pack(to_dev(b))
+    x = lat.field(qxd.F64, full=True)
+    for nkv in (6, 4):
+        prm = qxd.solver_params(res=1e-10, inner_prec=qxd.F32, sap_ncy=2, sap_nmr=8, sap_plain=1, nkv=nkv, nmx=400)
+        print("solving with restart length %d" % nkv, flush=True)
+        st = qxd.qxd_solve_fgcr(lat.h, prm, None, x, bd, check=False)
+        if st["status"] != 3:  # QXD_ENOMEM: try the shorter restart
+            break
+        qxd.qxd_trim(lat.h)
+        torch.cuda.empty_cache()
+    print("max-size SAP-FGCR(%d): %d steps, true residual %.2e" % (nkv, st["inner_it"], st["true_residual"]))
+    assert st["status"] == 0 and st["true_residual"] <= 1e-10
+    del bd
+    assert _oracle_residual(o, lat, x, b, 4) <= 1e-9
