@@ -72,6 +72,7 @@ extern "C" qxd_status qxd_create(const qxd_geom* g, qxd_handle** out) {
   if (!dev_alloc(&h->partial, h->npartial * sizeof(double)) ||
       !dev_alloc(&h->scal, QXD_NSCAL * sizeof(double)) ||
       hipHostMalloc(&h->scal_host, QXD_NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();  // the failed allocation is reported as QXD_ENOMEM only
     release(h);
     delete h;
     return QXD_ENOMEM;

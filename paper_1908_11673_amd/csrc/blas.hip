@@ -383,6 +383,7 @@ static_assert(QXD_MAXKV == 32, "QXD_K_CASES lists the basis sizes 0 .. QXD_MAXKV
 
 template <class VT>
 void blas_mdot(qxd_handle* h, const Ptrs& basis, int k, const VT* v, size_t n, double* slots, hipStream_t s) {
+  if (k == 0) return;  // no dots
   switch (k) {
 #define QXD_CASE(K)                                                                                             \
   case K:                                                                                                     \
@@ -421,6 +422,7 @@ void blas_r_update(qxd_handle* h, VT* r, const VT* v, size_t n, int i_c, double*
 }
 template <class VT>
 void blas_multi_axpy(qxd_handle* h, VT* x, const Ptrs& basis, int k, const double* coef, size_t n, hipStream_t s) {
+  if (k == 0) return;  // x unchanged
   switch (k) {
 #define QXD_CASE(K)                                                                                             \
   case K:                                                                                                     \

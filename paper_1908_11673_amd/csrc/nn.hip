@@ -267,7 +267,7 @@ struct NnTapList {
 // address of row rb's neighbour at (-1, -1, -1, d3); tap (d0, d1, d2, d3)
 // adds the constant (d0 + 1) T0 + (d1 + 1) T1 + (d2 + 1) T2.
 #ifndef NN_WPF
-#define NN_WPF 8
+#define NN_WPF 4  // taps ahead whose weights are in flight
 #endif
 #ifndef NN_WAVES
 #define NN_WAVES 8  // waves per workgroup of the block kernel
@@ -315,6 +315,11 @@ __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __r
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k % (NN_APF + 1)][rb], w[cb], acc[rb][cb], 0, 0, 0);
+    // keep each tap's prefetches in this tap: left free, the scheduler sinks
+    // every load next to its first use to save registers, and each tap then
+    // waits for its own weights and LDS operands (with half the taps, as on
+    // an input that vanishes on odd sites, the free schedule measured faster)
+    if (!SPARSE) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -441,9 +446,14 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
     // the weight loads do not depend on the block: keep the compiler from
-    // hoisting all 81 taps' worth out of the block loop
-    const uint16_t* Wb = W;
-    asm volatile("" : "+s"(Wb));
+    // hoisting all 81 taps' worth out of the block loop.  The opaque value is
+    // an offset, not the pointer: a pointer passed through the asm loses its
+    // global address space, and the flat loads the compiler then emits count
+    // against the LDS wait counter too, so every wait for an LDS operand
+    // would also wait for the weight loads in flight.
+    int wofs = 0;
+    asm volatile("" : "+s"(wofs));
+    const uint16_t* Wb = W + wofs;
     if (!SPARSE_IN || p == 0)
       nn_blk_taps<SH, SPARSE_IN, 0, RB, NCB>(lds, Wb, raddr, lr, kc, cb0, acc);
     else

@@ -150,3 +150,27 @@ def test_sap_fgcr_solves_at_max_size(biggest):
     assert st["status"] == 0 and st["true_residual"] <= 1e-10
     del bd
     assert _oracle_residual(o, lat, x, b, 4) <= 1e-9
+
+
+def test_enomem_leaves_no_hip_error_for_the_next_call(biggest):
+    """A solve whose vectors do not fit (FGCR with restart length 24 beside the
+    FP64 operator at the largest share: 48 FP32 directions of 3.2 GB) returns
+    QXD_ENOMEM, and the next call succeeds: the failed allocation is not
+    reported again as a HIP error (QXD_EHIP)."""
+    o, lat, psi = biggest
+    qxd.qxd_trim(lat.h)
+    torch.cuda.empty_cache()
+    b = sg.spinor(W["source_seed"] + 3, o.V)
+    bd = lat.pack(to_dev(b))
+    x = lat.field(qxd.F64, full=True)
+    st = qxd.qxd_solve_fgcr(lat.h, qxd.solver_params(res=1e-10, inner_prec=qxd.F32, nkv=24), None, x, bd,
+                            check=False)
+    print("FGCR(24) at the largest share: status %d" % st["status"])
+    assert st["status"] == 3  # QXD_ENOMEM
+    del bd, x
+    qxd.qxd_trim(lat.h)
+    torch.cuda.empty_cache()
+    sites = _sample(o, seed=5)
+    got = _apply(lat, psi, qxd.F64, 0, sites)  # raises on any status but QXD_OK
+    want = o.schur_sites(psi, sites)
+    assert float(np.abs(got - want).max() / np.abs(want).max()) < 1e-13

@@ -190,3 +190,4 @@ def test_zero_source_gives_the_zero_solution():
     qxd.qxd_dfl_destroy(d)
     qxd.qxd_nn_destroy(net)
     lat.close()
+
