@@ -317,9 +317,8 @@ __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __r
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k % (NN_APF + 1)][rb], w[cb], acc[rb][cb], 0, 0, 0);
     // keep each tap's prefetches in this tap: left free, the scheduler sinks
     // every load next to its first use to save registers, and each tap then
-    // waits for its own weights and LDS operands (with half the taps, as on
-    // an input that vanishes on odd sites, the free schedule measured faster)
-    if (!SPARSE) __builtin_amdgcn_sched_barrier(0);
+    // waits for its own weights and LDS operands
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
