@@ -146,6 +146,28 @@ def cpu_baseline(w, U, A, flav, seconds=15.0):
                       "lattice": "8x4^3 physical, C* 1"}}
 
 
+def solve_summary(tts):
+    """Per flavour of a time-to-solution block: FP64 CG, the network-preconditioned
+    mixed-precision FGCR and the fastest solve (all to the FP64 true residual
+    1e-10), with their speed-ups over FP64 CG."""
+    out = {}
+    for name, legs in tts.items():
+        if not isinstance(legs, dict):  # the lattice description
+            continue
+        ok = {k: v for k, v in legs.items() if isinstance(v, dict) and v.get("status") == 0 and "ms_median" in v}
+        if "cg_f64" not in ok:
+            continue
+        cg = ok["cg_f64"]["ms_median"]
+        best = min(ok, key=lambda k: ok[k]["ms_median"])
+        row = {"cg_f64_ms": cg, "fastest": best, "fastest_ms": ok[best]["ms_median"],
+               "fastest_speedup_vs_cg_f64": round(cg / ok[best]["ms_median"], 2)}
+        if "fgcr_f32_nn_in_f64" in ok:
+            nn = ok["fgcr_f32_nn_in_f64"]["ms_median"]
+            row.update({"mixed_learned_ms": nn, "mixed_learned_speedup_vs_cg_f64": round(cg / nn, 2)})
+        out[name] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +348,9 @@ def main():
     if not args.no_cpu_baseline and not big:  # the oracle would hold 60 GB of host fields at 128 x 64^3
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(w, U, A, flavours[0], args.cpu_seconds)
+    summary = {k: solve_summary(result[k]) for k in ("time_to_solution", "time_to_solution_c4") if k in result}
+    if summary:
+        result["solve_summary"] = summary
     print(json.dumps(result), flush=True)
     for lat in lats:
         lat.close()

@@ -143,6 +143,21 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_ms_r(double2* __restrict__ r, con
   }
 }
 
+// The shifts' vectors are addressed through pointers kept in LDS, which the
+// compiler cannot prove global: through a generic pointer the accesses would
+// become flat ones, which also count against the LDS wait counter, so every
+// read of a coefficient from LDS would wait for the vector loads in flight.
+// These helpers address them as global memory (non-temporal, as ld_stream).
+typedef __attribute__((address_space(1))) nt_d2 gl_nt_d2;
+__device__ inline double2 ld_shift(const double2* p) {
+  nt_d2 v = __builtin_nontemporal_load((const gl_nt_d2*)p);
+  return make_double2(v.x, v.y);
+}
+__device__ inline void st_shift(double2* p, double2 a) {
+  nt_d2 v = {a.x, a.y};
+  __builtin_nontemporal_store(v, (gl_nt_d2*)p);
+}
+
 // For every shift: x_j += a_j p_j (ACC: y += c_j a_j p_j instead), then
 // p_j = zeta_j r + b_j p_j while x_j is still updated; the base direction is
 // always advanced (p = r + b p).  Partial |p_base|^2.
@@ -175,24 +190,24 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_ms_update(VecPtrs P, VecPtrs X, d
     for (int j = 0; j < n; ++j) {
       const double flags = coef[3][j];
       if (flags == 0.0) continue;
-      double2 pj = ld_stream(&pp[j][i]);
+      double2 pj = ld_shift(&pp[j][i]);
       if (flags == 1.0 || flags == 3.0) {
         const double a = coef[0][j];
         if (ACC) {
           yi.x += a * pj.x;
           yi.y += a * pj.y;
         } else {
-          double2 xj = ld_stream(&xp[j][i]);
+          double2 xj = ld_shift(&xp[j][i]);
           xj.x += a * pj.x;
           xj.y += a * pj.y;
-          st_stream(&xp[j][i], xj);
+          st_shift(&xp[j][i], xj);
         }
       }
       if (flags >= 2.0) {
         const double z = coef[1][j], b = coef[2][j];
         pj.x = z * ri.x + b * pj.x;
         pj.y = z * ri.y + b * pj.y;
-        st_stream(&pp[j][i], pj);
+        st_shift(&pp[j][i], pj);
         if (j == base) acc += pj.x * pj.x + pj.y * pj.y;
       }
     }

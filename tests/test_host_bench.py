@@ -41,3 +41,23 @@ def test_recorded_traffic_follows_the_source_hash(monkeypatch, tmp_path):
     changed.write_bytes(open(os.path.join(ROOT, bench.TRAFFIC_SOURCES[0]), "rb").read() + b"\n")
     monkeypatch.setattr(bench, "TRAFFIC_SOURCES", (str(changed),) + tuple(bench.TRAFFIC_SOURCES[1:]))
     assert bench.recorded_traffic("dhat_f64") is None
+
+
+def test_solve_summary_picks_fastest_and_ratios():
+    """The summary of a time-to-solution block: FP64 CG, the network leg and the
+    fastest converged leg with their speed-ups; failed legs and non-leg entries
+    are ignored."""
+    tts = {"lattice": "some text",
+           "qhat-2": {"network_training": {"pairs": 10},
+                      "cg_f64": {"ms_median": 600.0, "status": 0},
+                      "fgcr_f32_in_f64": {"ms_median": 150.0, "status": 0},
+                      "fgcr_f32_sap_in_f64": {"ms_median": 100.0, "status": 0},
+                      "fgcr_f32_nn_in_f64": {"ms_median": 240.0, "status": 0},
+                      "fgcr_bf16links_in_f64": {"ms_median": 50.0, "status": 6}},
+           "qhat+4": {"fgcr_f32_in_f64": {"ms_median": 150.0, "status": 0}}}
+    s = bench.solve_summary(tts)
+    assert list(s) == ["qhat-2"]
+    row = s["qhat-2"]
+    assert row["fastest"] == "fgcr_f32_sap_in_f64" and row["fastest_ms"] == 100.0
+    assert row["fastest_speedup_vs_cg_f64"] == 6.0
+    assert row["mixed_learned_ms"] == 240.0 and row["mixed_learned_speedup_vs_cg_f64"] == 2.5
