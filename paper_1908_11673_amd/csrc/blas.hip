@@ -260,11 +260,12 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_scale_cdot(VT* __restrict__ v, co
   if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = s;
 }
 
-// r -= c v (c complex at scal[i_c]); partial |r|^2
+// r -= c v (c complex at scal[i_c]), also written to r_copy unless that is
+// null; partial |r|^2
 template <class VT>
 __global__ __launch_bounds__(QXD_BLOCK) void k_r_update(VT* __restrict__ r, const VT* __restrict__ v, size_t n,
                                                         const double* __restrict__ scal, int i_c,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial, VT* __restrict__ r_copy) {
   __shared__ double sh[QXD_BLOCK / 64];
   double cr = scal[i_c], ci = scal[i_c + 1];
   double a = 0.0;
@@ -272,6 +273,7 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_r_update(VT* __restrict__ r, cons
              [&](size_t i, W2<VT> w) {
                VT ri = wcaxpy(w.a, -cr, -ci, w.b);
                st_stream(&r[i], ri);
+               if (r_copy) st_stream(&r_copy[i], ri);
                a += wnorm2(ri);
              });
   double s = red_block(a, sh);
@@ -416,8 +418,9 @@ void blas_scale_cdot(qxd_handle* h, VT* v, const VT* r, size_t n, int i_n2, doub
   launch_final_sum(h->partial, QXD_NRED, 2, QXD_NRED, slots, s);
 }
 template <class VT>
-void blas_r_update(qxd_handle* h, VT* r, const VT* v, size_t n, int i_c, double* slot, hipStream_t s) {
-  hipLaunchKernelGGL(k_r_update<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, r, v, n, h->scal, i_c, h->partial);
+void blas_r_update(qxd_handle* h, VT* r, const VT* v, size_t n, int i_c, double* slot, hipStream_t s, VT* r_copy) {
+  hipLaunchKernelGGL(k_r_update<VT>, dim3(QXD_NRED), dim3(QXD_BLOCK), 0, s, r, v, n, h->scal, i_c, h->partial,
+                     r_copy);
   launch_final_sum(h->partial, QXD_NRED, 1, QXD_NRED, slot, s);
 }
 template <class VT>
@@ -455,7 +458,7 @@ void blas_up_acc(qxd_handle* h, double2* x, const float4* e, int i_n2, hipStream
   template void blas_mupdate<VT>(qxd_handle*, VT*, const Ptrs&, int, const double*, size_t, double*,    \
                                  hipStream_t);                                                          \
   template void blas_scale_cdot<VT>(qxd_handle*, VT*, const VT*, size_t, int, double*, hipStream_t);    \
-  template void blas_r_update<VT>(qxd_handle*, VT*, const VT*, size_t, int, double*, hipStream_t);      \
+  template void blas_r_update<VT>(qxd_handle*, VT*, const VT*, size_t, int, double*, hipStream_t, VT*); \
   template void blas_multi_axpy<VT>(qxd_handle*, VT*, const Ptrs&, int, const double*, size_t,          \
                                     hipStream_t);                                                       \
   template void blas_zero<VT>(VT*, size_t, hipStream_t);

@@ -25,7 +25,10 @@ void blas_mupdate(qxd_handle* h, VT* v, const Ptrs& basis, int k, const double* 
                   hipStream_t s);
 template <class VT>
 void blas_scale_cdot(qxd_handle* h, VT* v, const VT* r, size_t n, int i_n2, double* slots, hipStream_t s);
-template <class VT> void blas_r_update(qxd_handle* h, VT* r, const VT* v, size_t n, int i_c, double* slot, hipStream_t s);
+// r -= c v; with r_copy the new r is written there too
+template <class VT>
+void blas_r_update(qxd_handle* h, VT* r, const VT* v, size_t n, int i_c, double* slot, hipStream_t s,
+                   VT* r_copy = nullptr);
 template <class VT>
 void blas_multi_axpy(qxd_handle* h, VT* x, const Ptrs& basis, int k, const double* coef, size_t n, hipStream_t s);
 template <class VT> void blas_zero(VT* x, size_t n, hipStream_t s);

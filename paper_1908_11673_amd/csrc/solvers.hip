@@ -158,7 +158,12 @@ struct FgcrResult {
 // Flexible GCR on op x = b, x starting at zero; r holds b on entry and the
 // recursive residual on exit.  Classical Gram-Schmidt of chi_k against the
 // previous directions, normalisation, then r -= (chi_k, r) chi_k; at the end of
-// each cycle x += Phi alpha with R alpha = c solved on the host in FP64.
+// each cycle x += Phi alpha with R alpha = c solved on the host in FP64.  The
+// host waits once per step, for |chi_k|^2 and |r|^2 together: a direction whose
+// norm is zero or not finite is zeroed by the normalisation, so the residual
+// update leaves r as it was and the step can be redone without the
+// preconditioner.  Without a preconditioner phi_k = r_k, and the residual
+// update of step k writes r_{k+1} to phi_{k+1} as well (phi_0 is a copy).
 template <class VT>
 qxd_status fgcr(qxd_handle* h, InnerOp op, Precond pc, int fallback_after, VT* x, VT* r, size_t n, int nkv,
                 double tol_abs, int max_steps, FgcrResult* res, hipStream_t s,
@@ -176,6 +181,7 @@ qxd_status fgcr(qxd_handle* h, InnerOp op, Precond pc, int fallback_after, VT* x
   double rr = h->scal_host[S_FRR];
   if (!std::isfinite(rr)) return QXD_ENAN;
   bool use_nn = pc.any();
+  bool r_in_phi = false;  // phi[k] already holds r (written by the previous residual update)
   double best = std::sqrt(rr);
   int since_best = 0;
   int steps = 0;
@@ -191,7 +197,7 @@ qxd_status fgcr(qxd_handle* h, InnerOp op, Precond pc, int fallback_after, VT* x
             res->nn_applies++;
           else
             res->sap_applies++;
-        } else {
+        } else if (k == 0 || !r_in_phi) {
           QXD_HIP(hipMemcpyAsync(phi[k], r, bytes, hipMemcpyDeviceToDevice, s));
         }
         if (k == 0) {
@@ -205,9 +211,17 @@ qxd_status fgcr(qxd_handle* h, InnerOp op, Precond pc, int fallback_after, VT* x
           blas_mupdate<VT>(h, chi[k], bp, k, col, n, h->scal + S_FB + k, s);
         }
         res->applies++;
-        QXD_TRY(read_scal(h, S_FB + k, 1, s));
+        blas_scale_cdot<VT>(h, chi[k], r, n, S_FB + k, h->scal + S_FC + 2 * k, s);
+        // plain FGCR: the next step's phi is the new residual
+        r_in_phi = !use_nn && k + 1 < nkv;
+        blas_r_update<VT>(h, r, chi[k], n, S_FC + 2 * k, h->scal + S_FRR, s, r_in_phi ? phi[k + 1] : nullptr);
+        QXD_HIP(hipMemcpyAsync(h->scal_host + S_FB + k, h->scal + S_FB + k, sizeof(double), hipMemcpyDeviceToHost,
+                               s));
+        QXD_TRY(read_scal(h, S_FRR, 1, s));
         double b2 = h->scal_host[S_FB + k];
         if (!std::isfinite(b2) || !(b2 > 0.0)) {
+          // chi_k was zeroed and r is unchanged
+          r_in_phi = false;
           if (use_nn) {  // the preconditioner produced a useless direction: drop it, redo the step plainly
             use_nn = false;
             res->fell_back = true;
@@ -217,9 +231,6 @@ qxd_status fgcr(qxd_handle* h, InnerOp op, Precond pc, int fallback_after, VT* x
           return std::isfinite(b2) ? QXD_ENOCONV : QXD_ENAN;
         }
       }
-      blas_scale_cdot<VT>(h, chi[k], r, n, S_FB + k, h->scal + S_FC + 2 * k, s);
-      blas_r_update<VT>(h, r, chi[k], n, S_FC + 2 * k, h->scal + S_FRR, s);
-      QXD_TRY(read_scal(h, S_FRR, 1, s));
       rr = h->scal_host[S_FRR];
       ++m;
       ++steps;
