@@ -374,13 +374,14 @@ __device__ __forceinline__ void nn_halo_stage(const Geo& g, const uint16_t* __re
   }
 }
 
-// Persistent block-tiled convolution: a workgroup of 4 waves (one per SIMD)
-// walks blocks, and the workgroups of one XCD walk one contiguous eighth of the
-// block list together, so neighbouring blocks share that XCD's L2.  A wave owns
-// 8 row tiles of 16 same-parity sites (128 sites; the last layer: 4 tiles of
-// even sites) and all 32 output channels, so each weight tile it loads feeds
-// 16 matrix-core instructions.  Per block: halo to LDS, taps, output tile
-// staged in LDS, coalesced stores.
+// Persistent block-tiled convolution: a workgroup of NW = 8 waves (two per
+// SIMD, one workgroup per CU) walks blocks, and the workgroups of one XCD walk
+// one contiguous eighth of the block list together, so neighbouring blocks
+// share that XCD's L2.  A wave owns 4 row tiles of 16 same-parity sites (64
+// sites) and both column tiles of 16 output channels, so each weight tile it
+// loads feeds 4 matrix-core instructions and each operand it reads from LDS 2
+// (the last layer: 4 tiles of even sites and one column tile per wave).  Per
+// block: halo to LDS, taps, output tile staged in LDS, coalesced stores.
 template <int NW, int EPI, bool SPARSE_IN, bool EVEN_OUT>
 __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint16_t* __restrict__ in,
                                                  const uint16_t* __restrict__ W, uint16_t* __restrict__ out_act,
