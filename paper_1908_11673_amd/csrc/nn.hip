@@ -263,7 +263,8 @@ struct NnTapList {
 
 // The tap loop, fully unrolled: the weights of tap k + NN_WPF and the LDS
 // operands of tap k + NN_APF are requested while tap k is contracted, on NCB
-// column tiles of 16 output channels starting at tile cb0.  raddr[rb][d3 + 1] is the byte
+// column tiles of 16 output channels starting at tile cb0; side(k) issues
+// further loads of the caller's (the next block's halo) in tap k.  raddr[rb][d3 + 1] is the byte
 // address of row rb's neighbour at (-1, -1, -1, d3); tap (d0, d1, d2, d3)
 // adds the constant (d0 + 1) T0 + (d1 + 1) T1 + (d2 + 1) T2.
 #ifndef NN_WPF
@@ -275,9 +276,9 @@ struct NnTapList {
 #ifndef NN_APF
 #define NN_APF 2  // taps ahead whose LDS operands are in flight
 #endif
-template <class SH, bool SPARSE, int P, int RB, int NCB>
+template <class SH, bool SPARSE, int P, int RB, int NCB, class PF>
 __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __restrict__ W, const int (&raddr)[RB][3],
-                                            int lr, int kc, int cb0, f4v (&acc)[RB][NCB]) {
+                                            int lr, int kc, int cb0, f4v (&acc)[RB][NCB], PF&& side) {
   constexpr NnTapList<SPARSE, P> TL{};
   static_assert(TL.n > NN_WPF && TL.n > NN_APF, "prefetch deeper than the tap list");
   auto wld = [&](int tap, int cb) {
@@ -297,7 +298,9 @@ __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __r
   for (int k = 0; k < NN_APF; ++k)
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) a[k][rb] = rd(rb, TL.t[k]);
-#pragma unroll
+  // an explicit count: a plain full-unroll request is dropped above LLVM's
+  // size limit, which this loop body with its halo loads exceeds
+#pragma unroll TL.n
   for (int k = 0; k < TL.n; ++k) {
     bf16x8 w[NCB];
 #pragma unroll
@@ -306,6 +309,7 @@ __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __r
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) wb[k % NN_WPF][cb] = wld(TL.t[k + NN_WPF], cb);
     }
+    side(k);
     if (k + NN_APF < TL.n) {
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) a[(k + NN_APF) % (NN_APF + 1)][rb] = rd(rb, TL.t[k + NN_APF]);
@@ -322,57 +326,50 @@ __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __r
   }
 }
 
-// Halo of the block with origin o, staged through registers in two halves:
-// this thread moves chunk threadIdx & 3 of the positions threadIdx / 4 + 64 k.
-// Positions past the halo and skipped odd sites read the first site; they are
-// written to LDS but never read.  Every load of a half is issued before its
-// first LDS write.
+// Halo of the block with origin o, moved through registers: this thread
+// moves chunk threadIdx & 3 of the positions threadIdx / 4 + GRP k, k < HPT.
+// Positions past the halo and skipped odd sites read the first site; they
+// are written to LDS but never read.
 template <class SH, int NW, bool SPARSE_IN>
-__device__ __forceinline__ void nn_halo_stage(const Geo& g, const uint16_t* __restrict__ in, char* lds, int o0,
-                                              int o1, int o2, int o3) {
-  constexpr int GRP = 16 * NW;                       // positions per pass of the workgroup
-  constexpr int HPT = (SH::NPOS + GRP - 1) / GRP;    // positions per thread
+struct NnHalo {
+  static constexpr int GRP = 16 * NW;                     // positions per pass of the workgroup
+  static constexpr int HPT = (SH::NPOS + GRP - 1) / GRP;  // positions per thread
   static_assert(HPT * GRP * 64 <= SH::LDS_BYTES, "halo staging");
-  constexpr int HALF = NW >= 8 ? HPT : (HPT + 1) / 2;
-  const int hc = threadIdx.x & 3;
-#pragma unroll
-  for (int k0 = 0; k0 < HPT; k0 += HALF) {
-    uint4 hv[HALF];
-#pragma unroll
-    for (int k = 0; k < HALF; ++k) {
-      int pos = (threadIdx.x >> 2) + GRP * (k0 + k);
-      bool ok = pos < SH::NPOS;
-      int h3 = pos % SH::H3, r = pos / SH::H3;
-      int h2 = r % SH::H2;
-      r /= SH::H2;
-      int h1 = r % SH::H1, h0 = r / SH::H1;
-      int x0 = o0 + h0 - 1, x1 = o1 + h1 - 1, x2 = o2 + h2 - 1, x3 = o3 + h3 - 1;
-      x0 = x0 < 0 ? x0 + g.Le0 : (x0 >= g.Le0 ? x0 - g.Le0 : x0);
-      x1 = x1 < 0 ? x1 + g.Le1 : (x1 >= g.Le1 ? x1 - g.Le1 : x1);
-      bool mir = false;
-      if (x2 < 0 || x2 >= g.Le2) {
-        x2 = x2 < 0 ? x2 + g.Le2 : x2 - g.Le2;
-        mir = g.cstar >= 2;
-      }
-      if (x3 < 0 || x3 >= g.Le3) {
-        x3 = x3 < 0 ? x3 + g.Le3 : x3 - g.Le3;
-        if (g.cstar >= 3) mir = !mir;
-      }
-      if (mir) x1 = geo_mirror_x1(g, x1);
-      int par = (x0 + x1 + x2 + x3) & 1;
-      ok = ok && !(SPARSE_IN && par) && k0 + k < HPT;
-      size_t q = ok ? (size_t)par * g.Ve + geo_half(g, x0, x1, x2, x3) : 0;
-      hv[k] = reinterpret_cast<const uint4*>(in + q * NN_C)[hc];
+  __device__ static __forceinline__ uint4 load(const Geo& g, const uint16_t* __restrict__ in, int o0, int o1, int o2,
+                                               int o3, int k) {
+    int pos = (threadIdx.x >> 2) + GRP * k;
+    // opaque: otherwise the block-independent coordinates of all HPT
+    // positions are hoisted out of the block loop and held in registers
+    asm volatile("" : "+v"(pos));
+    bool ok = pos < SH::NPOS;
+    int h3 = pos % SH::H3, r = pos / SH::H3;
+    int h2 = r % SH::H2;
+    r /= SH::H2;
+    int h1 = r % SH::H1, h0 = r / SH::H1;
+    int x0 = o0 + h0 - 1, x1 = o1 + h1 - 1, x2 = o2 + h2 - 1, x3 = o3 + h3 - 1;
+    x0 = x0 < 0 ? x0 + g.Le0 : (x0 >= g.Le0 ? x0 - g.Le0 : x0);
+    x1 = x1 < 0 ? x1 + g.Le1 : (x1 >= g.Le1 ? x1 - g.Le1 : x1);
+    bool mir = false;
+    if (x2 < 0 || x2 >= g.Le2) {
+      x2 = x2 < 0 ? x2 + g.Le2 : x2 - g.Le2;
+      mir = g.cstar >= 2;
     }
-#pragma unroll
-    for (int k = 0; k < HALF; ++k) {
-      if (k0 + k >= HPT) break;
-      int pos = (threadIdx.x >> 2) + GRP * (k0 + k);
-      int h3 = pos % SH::H3;
-      *reinterpret_cast<uint4*>(lds + pos * 64 + ((hc ^ ((h3 >> 1) & 3)) << 4)) = hv[k];
+    if (x3 < 0 || x3 >= g.Le3) {
+      x3 = x3 < 0 ? x3 + g.Le3 : x3 - g.Le3;
+      if (g.cstar >= 3) mir = !mir;
     }
+    if (mir) x1 = geo_mirror_x1(g, x1);
+    int par = (x0 + x1 + x2 + x3) & 1;
+    ok = ok && !(SPARSE_IN && par);
+    size_t q = ok ? (size_t)par * g.Ve + geo_half(g, x0, x1, x2, x3) : 0;
+    return reinterpret_cast<const uint4*>(in + q * NN_C)[threadIdx.x & 3];
   }
-}
+  __device__ static __forceinline__ void store(char* lds, int k, const uint4& v) {
+    int pos = (threadIdx.x >> 2) + GRP * k;
+    int h3 = pos % SH::H3;
+    *reinterpret_cast<uint4*>(lds + pos * 64 + (((threadIdx.x & 3) ^ ((h3 >> 1) & 3)) << 4)) = v;
+  }
+};
 
 // Persistent block-tiled convolution: a workgroup of NW = 8 waves (two per
 // SIMD, one workgroup per CU) walks blocks, and the workgroups of one XCD walk
@@ -381,7 +378,8 @@ __device__ __forceinline__ void nn_halo_stage(const Geo& g, const uint16_t* __re
 // sites) and both column tiles of 16 output channels, so each weight tile it
 // loads feeds 4 matrix-core instructions and each operand it reads from LDS 2
 // (the last layer: 4 tiles of even sites and one column tile per wave).  Per
-// block: halo to LDS, taps, output tile staged in LDS, coalesced stores.
+// block: taps (with the next block's halo loads), output tile staged in LDS,
+// coalesced stores, the next halo from registers to LDS.
 template <int NW, int EPI, bool SPARSE_IN, bool EVEN_OUT>
 __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint16_t* __restrict__ in,
                                                  const uint16_t* __restrict__ W, uint16_t* __restrict__ out_act,
@@ -435,11 +433,36 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
     if (rin) skc = scal2 ? (float)(skip / sqrt(scal2[i_s2])) : skip;
   }
 
+  // The halo of the next block is loaded into registers during the taps of
+  // the current one (HPT loads per thread, one per tap) and written to the LDS
+  // once its output tile has left: the loads of all workgroups then spread
+  // over the matrix-core work instead of arriving at memory in one burst per
+  // block.
+  using HL = NnHalo<SH, NW, SPARSE_IN>;
+  // one halo load every HS taps, spread over the tap loop
+  constexpr int NTAP0 = NnTapList<SPARSE_IN, 0>{}.n, NTAP1 = NnTapList<SPARSE_IN, 1>{}.n;
+  constexpr int HS = (NTAP0 < NTAP1 ? NTAP0 : NTAP1) / HL::HPT;
+  static_assert(HS >= 1, "one halo load per tap at most");
+  uint4 hv[HL::HPT];
+  if (bbeg + wi < bend) {
+    int o0, o1, o2, o3;
+    origin(bbeg + wi, o0, o1, o2, o3);
+#pragma unroll
+    for (int k = 0; k < HL::HPT; ++k) hv[k] = HL::load(g, in, o0, o1, o2, o3, k);
+#pragma unroll
+    for (int k = 0; k < HL::HPT; ++k) HL::store(lds, k, hv[k]);
+  }
+  __syncthreads();
+
   for (int b = bbeg + wi; b < bend; b += nwx) {
     int o0, o1, o2, o3;
     origin(b, o0, o1, o2, o3);
-    nn_halo_stage<SH, NW, SPARSE_IN>(g, in, lds, o0, o1, o2, o3);
-    __syncthreads();
+    // the next block of this workgroup (the last one loads a block it does not use)
+    int n0, n1h, n2h, n3h;
+    origin(min(b + nwx, bend - 1), n0, n1h, n2h, n3h);
+    auto side = [&](int k) {
+      if (k % HS == 0 && k / HS < HL::HPT) hv[k / HS] = HL::load(g, in, n0, n1h, n2h, n3h, k / HS);
+    };
     f4v acc[RB][NCB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -455,9 +478,9 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
     asm volatile("" : "+s"(wofs));
     const uint16_t* Wb = W + wofs;
     if (!SPARSE_IN || p == 0)
-      nn_blk_taps<SH, SPARSE_IN, 0, RB, NCB>(lds, Wb, raddr, lr, kc, cb0, acc);
+      nn_blk_taps<SH, SPARSE_IN, 0, RB, NCB>(lds, Wb, raddr, lr, kc, cb0, acc, side);
     else
-      nn_blk_taps<SH, SPARSE_IN, 1, RB, NCB>(lds, Wb, raddr, lr, kc, cb0, acc);
+      nn_blk_taps<SH, SPARSE_IN, 1, RB, NCB>(lds, Wb, raddr, lr, kc, cb0, acc, side);
     __syncthreads();  // every wave is done with the halo: the LDS takes the output tile
     const int hb = geo_half(g, o0, o1, o2, o3);
     if (EPI == EPI_SPINOR) {
@@ -532,6 +555,11 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
       }
     }
     __syncthreads();  // the output tile has left the LDS
+    if (b + nwx < bend) {
+#pragma unroll
+      for (int k = 0; k < HL::HPT; ++k) HL::store(lds, k, hv[k]);
+    }
+    __syncthreads();
   }
 }
 
