@@ -262,7 +262,7 @@ struct NnTapList {
 };
 
 // The tap loop, fully unrolled: the weights of tap k + NN_WPF and the LDS
-// operands of tap k + NN_APF are requested while tap k is contracted, on NCB
+// operands of tap k + APF are requested while tap k is contracted, on NCB
 // column tiles of 16 output channels starting at tile cb0; side(k) issues
 // further loads of the caller's (the next block's halo) in tap k.  raddr[rb][d3 + 1] is the byte
 // address of row rb's neighbour at (-1, -1, -1, d3); tap (d0, d1, d2, d3)
@@ -280,7 +280,9 @@ template <class SH, bool SPARSE, int P, int RB, int NCB, class PF>
 __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __restrict__ W, const int (&raddr)[RB][3],
                                             int lr, int kc, int cb0, f4v (&acc)[RB][NCB], PF&& side) {
   constexpr NnTapList<SPARSE, P> TL{};
-  static_assert(TL.n > NN_WPF && TL.n > NN_APF, "prefetch deeper than the tap list");
+  // LDS operands of APF taps ahead: 8 row tiles hold 32 registers per tap in flight
+  constexpr int APF = RB >= 8 ? 1 : NN_APF;
+  static_assert(TL.n > NN_WPF && TL.n > APF, "prefetch deeper than the tap list");
   auto wld = [&](int tap, int cb) {
     return ld8(W + tap * (NN_C * NN_C) + ((cb0 + cb) * 16 + lr) * NN_C + kc);
   };
@@ -293,9 +295,9 @@ __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __r
   for (int k = 0; k < NN_WPF; ++k)
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) wb[k][cb] = wld(TL.t[k], cb);
-  bf16x8 a[NN_APF + 1][RB];
+  bf16x8 a[APF + 1][RB];
 #pragma unroll
-  for (int k = 0; k < NN_APF; ++k)
+  for (int k = 0; k < APF; ++k)
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) a[k][rb] = rd(rb, TL.t[k]);
   // an explicit count: a plain full-unroll request is dropped above LLVM's
@@ -310,15 +312,15 @@ __device__ __forceinline__ void nn_blk_taps(const char* lds, const uint16_t* __r
       for (int cb = 0; cb < NCB; ++cb) wb[k % NN_WPF][cb] = wld(TL.t[k + NN_WPF], cb);
     }
     side(k);
-    if (k + NN_APF < TL.n) {
+    if (k + APF < TL.n) {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) a[(k + NN_APF) % (NN_APF + 1)][rb] = rd(rb, TL.t[k + NN_APF]);
+      for (int rb = 0; rb < RB; ++rb) a[(k + APF) % (APF + 1)][rb] = rd(rb, TL.t[k + APF]);
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k % (NN_APF + 1)][rb], w[cb], acc[rb][cb], 0, 0, 0);
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k % (APF + 1)][rb], w[cb], acc[rb][cb], 0, 0, 0);
     // keep each tap's prefetches in this tap: left free, the scheduler sinks
     // every load next to its first use to save registers, and each tap then
     // waits for its own weights and LDS operands
@@ -374,12 +376,15 @@ struct NnHalo {
 // Persistent block-tiled convolution: a workgroup of NW = 8 waves (two per
 // SIMD, one workgroup per CU) walks blocks, and the workgroups of one XCD walk
 // one contiguous eighth of the block list together, so neighbouring blocks
-// share that XCD's L2.  A wave owns 4 row tiles of 16 same-parity sites (64
-// sites) and both column tiles of 16 output channels, so each weight tile it
-// loads feeds 4 matrix-core instructions and each operand it reads from LDS 2
-// (the last layer: 4 tiles of even sites and one column tile per wave).  Per
-// block: taps (with the next block's halo loads), output tile staged in LDS,
-// coalesced stores, the next halo from registers to LDS.
+// share that XCD's L2.  A wave owns 8 row tiles of 16 same-parity sites (128
+// sites) and one column tile of 16 output channels, so each weight tile it
+// loads feeds 8 matrix-core instructions (the last layer: 4 tiles of even
+// sites).  Each operand read from LDS feeds one instruction: the LDS has the
+// bandwidth to spare, the vector memory path that brings the weights has
+// not (half the weight loads of a wave owning both column tiles of 4 row
+// tiles, for twice the LDS reads).  Per block: taps (with the next block's
+// halo loads), output tile staged in LDS, coalesced stores, the next halo
+// from registers to LDS.
 template <int NW, int EPI, bool SPARSE_IN, bool EVEN_OUT>
 __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint16_t* __restrict__ in,
                                                  const uint16_t* __restrict__ W, uint16_t* __restrict__ out_act,
@@ -409,16 +414,15 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
     o3 = c3 * SH::B3;
   };
 
-  // NW waves share the 32 row tiles (16 of each parity) and both column tiles;
-  // with EVEN_OUT the 16 even row tiles, each wave one column tile (so that a
-  // weight tile loaded still feeds as many matrix-core instructions)
-  constexpr int NCB = EVEN_OUT ? 1 : 2;
-  constexpr int RB = 32 / NW;
+  // NW waves share the 32 row tiles (16 of each parity) and the two column
+  // tiles, each wave one column tile; with EVEN_OUT the 16 even row tiles
+  constexpr int NCB = 1;
+  constexpr int RB = EVEN_OUT ? 32 / NW : 64 / NW;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int lr = l & 15, kc = (l >> 4) * 8, ch = l >> 4;
   const int p = EVEN_OUT ? 0 : wave / (NW / 2);
-  const int cb0 = EVEN_OUT ? (wave & 1) : 0;
-  const int g0 = EVEN_OUT ? (wave >> 1) : wave % (NW / 2), gstep = NW / 2;
+  const int cb0 = wave & 1;
+  const int g0 = EVEN_OUT ? (wave >> 1) : (wave % (NW / 2)) >> 1, gstep = EVEN_OUT ? NW / 2 : NW / 4;
   int raddr[RB][3];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
