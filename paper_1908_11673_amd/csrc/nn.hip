@@ -568,25 +568,24 @@ __global__ __launch_bounds__(64 * NW) void k_conv_ws(Geo g, int nblk, const uint
 }
 
 // layer-1 input: even sites carry r / |r| (channel 2c + 0/1 = Re/Im of
-// component c), odd sites and channels 24..31 are zero
+// component c), odd sites and channels 24..31 are zero.  Only channels 0..23
+// of the even sites are written here: the rest of a0 is zeroed once when it
+// is allocated and never written.
 __global__ __launch_bounds__(256) void k_nn_embed(Geo g, const float4* __restrict__ r, const double* __restrict__ scal,
                                                   int i_n2, uint16_t* __restrict__ a0) {
   int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= 2 * g.Ve) return;
-  uint16_t v[NN_C];
-  for (int c = 0; c < NN_C; ++c) v[c] = 0;
-  if (q < g.Ve) {
-    float s = scal ? (float)(1.0 / sqrt(scal[i_n2])) : 1.0f;
-    for (int j = 0; j < 6; ++j) {
-      float4 x = r[(size_t)j * g.Ve + q];
-      v[4 * j] = f2bf(s * x.x);
-      v[4 * j + 1] = f2bf(s * x.y);
-      v[4 * j + 2] = f2bf(s * x.z);
-      v[4 * j + 3] = f2bf(s * x.w);
-    }
+  if (q >= g.Ve) return;
+  uint16_t v[24];
+  float s = scal ? (float)(1.0 / sqrt(scal[i_n2])) : 1.0f;
+  for (int j = 0; j < 6; ++j) {
+    float4 x = r[(size_t)j * g.Ve + q];
+    v[4 * j] = f2bf(s * x.x);
+    v[4 * j + 1] = f2bf(s * x.y);
+    v[4 * j + 2] = f2bf(s * x.z);
+    v[4 * j + 3] = f2bf(s * x.w);
   }
   uint4* o = reinterpret_cast<uint4*>(a0 + (size_t)q * NN_C);
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < 3; ++k)
     o[k] = make_uint4(v[8 * k] | (v[8 * k + 1] << 16), v[8 * k + 2] | (v[8 * k + 3] << 16),
                       v[8 * k + 4] | (v[8 * k + 5] << 16), v[8 * k + 6] | (v[8 * k + 7] << 16));
 }
@@ -836,18 +835,20 @@ static void nn_free_all(std::initializer_list<void**> ptrs) {
   }
 }
 
-static qxd_status nn_alloc_act(qxd_nn* net) {
+static qxd_status nn_alloc_act(qxd_nn* net, hipStream_t s) {
   if (net->a0) return QXD_OK;
   size_t bytes = (size_t)net->h->V * NN_C * sizeof(uint16_t);
   if (!dev_alloc(&net->a0, bytes) || !dev_alloc(&net->a1, bytes) || !dev_alloc(&net->a2, bytes)) {
     nn_free_all({(void**)&net->a0, (void**)&net->a1, (void**)&net->a2});
     return QXD_ENOMEM;
   }
+  // the odd sites and channels 24..31 of a0 are never written: zero once
+  QXD_HIP(hipMemsetAsync(net->a0, 0, bytes, s));
   return QXD_OK;
 }
 
 static qxd_status nn_alloc_train(qxd_nn* net, hipStream_t s) {
-  QXD_TRY(nn_alloc_act(net));
+  QXD_TRY(nn_alloc_act(net, s));
   if (net->g3) return QXD_OK;
   qxd_handle* h = net->h;
   size_t bytes = (size_t)h->V * NN_C * sizeof(uint16_t);
@@ -869,9 +870,9 @@ static qxd_status nn_alloc_train(qxd_nn* net, hipStream_t s) {
 // forward pass on r (F32 even half): activations a0, a1, a2 and output
 // out = scale * N(r / |r|) (scale = |r| when with_norm, else 1 and no input scaling)
 static qxd_status nn_forward(qxd_handle* h, qxd_nn* net, const float4* r, float* out, bool with_norm, hipStream_t s) {
-  QXD_TRY(nn_alloc_act(net));
+  QXD_TRY(nn_alloc_act(net, s));
   if (with_norm) blas_norm2<float4>(h, r, (size_t)6 * h->Ve, h->scal + S_NN, s);
-  hipLaunchKernelGGL(k_nn_embed, dim3(div_up(2 * h->Ve, 256)), dim3(256), 0, s, h->geo, r,
+  hipLaunchKernelGGL(k_nn_embed, dim3(div_up(h->Ve, 256)), dim3(256), 0, s, h->geo, r,
                      with_norm ? h->scal : nullptr, S_NN, net->a0);
   conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s, nullptr, 0.f,
               nullptr, 0, net);
@@ -899,7 +900,7 @@ static qxd_status nn_pair(qxd_handle* h, qxd_nn* net, const float4* r, const flo
   blas_norm2<float4>(h, r, nw, h->scal + slot, s);
   blas_norm2<float4>(h, e, nw, h->scal + slot + 1, s);
   // forward on r / |r| (scale 1 at the output): y = N(rhat)
-  hipLaunchKernelGGL(k_nn_embed, dim3(div_up(2 * h->Ve, 256)), dim3(256), 0, s, h->geo, r, h->scal, slot, net->a0);
+  hipLaunchKernelGGL(k_nn_embed, dim3(div_up(h->Ve, 256)), dim3(256), 0, s, h->geo, r, h->scal, slot, net->a0);
   conv_launch(h, 0, net->a0, net->wf, (int)h->V, EPI_RELU, net->a1, nullptr, nullptr, nullptr, 0, s, nullptr, 0.f,
               nullptr, 0, net);
   conv_launch(h, 1, net->a1, net->wf, (int)h->V, EPI_RELU, net->a2, nullptr, nullptr, nullptr, 0, s, nullptr, 0.f,
