@@ -6,7 +6,14 @@ checked on sampled even sites against the network oracle evaluated site by
 site in its bfloat16 storage mode (weights, input and ReLU outputs rounded
 where the kernels store them) on the FP32-rounded input: 2e-3 in norm, the
 bar of the small-lattice tests (measured 1.6e-4), and 5e-3 for the worst
-single site against the rms output (measured 7.2e-4)."""
+single site against the rms output (measured 7.2e-4).
+
+The same check on the 36 x 8 x 16 x 32 physical lattice (extended 36 x 16 x
+16 x 32, 576 blocks): there the workgroups of an XCD walk 72 blocks, eight of
+them three blocks and the others two, so the halo loaded for a next block,
+the last block of a workgroup and the uneven split all occur (measured 1.8e-4
+in norm, 7.1e-4 for the worst site), and a second application gives the same
+bits."""
 import numpy as np
 import pytest
 
@@ -73,5 +80,56 @@ def test_network_apply_full_size_sampled(full, skip):
     rms = np.linalg.norm(want) / np.sqrt(len(sites))
     worst = np.linalg.norm((got - want).reshape(len(sites), -1), axis=1).max() / rms
     print("skip %.2f: %d sampled sites, rel err %.2e, worst site %.2e of the rms" % (skip, len(sites), err, worst))
+    assert err < 2e-3
+    assert worst < 5e-3
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    L, cstar = (36, 8, 16, 32), 3
+    vphys = int(np.prod(L))
+    U = sg.gauge_su3(W["gauge_seed"] + 1, W["sigma_su3"], vphys)
+    A = sg.gauge_u1(W["gauge_seed"] + 1, W["sigma_u1"], vphys)
+    lat = qxd.Lattice(L, cstar)
+    lat.setup(U, A, sg.FLAVOURS["u"])
+    del U, A
+    o = oracle.Oracle(L, cstar)
+    nb, _ = o.neighbours()
+    par = o.parity()
+    even = np.nonzero(par == 0)[0]
+    # corners of the lattice and sites on the faces of the last blocks
+    corners = o.site(np.array([[0, 0, 0, 0], [o.Le[0] - 1, o.Le[1] - 1, 0, 0], [o.Le[0] - 2, o.L[1], o.Le[2] - 1, 1],
+                               [o.Le[0] - 4, o.Le[1] - 1, o.Le[2] - 4, o.Le[3] - 1], [32, 0, 3, o.Le[3] - 8]]))
+    sites = np.concatenate([corners[par[corners] == 0], np.random.default_rng(4).choice(even, 48, replace=False)])
+    yield o, lat, nb, sites
+    lat.close()
+
+
+def test_network_apply_uneven_block_split_sampled(ragged):
+    o, lat, nb, sites = ragged
+    ws = init_weights(6)
+    net = qxd.qxd_nn_create(lat.h)
+    qxd.qxd_nn_set_weights(net, np.concatenate([w.reshape(-1) for w in ws]).astype(np.float32))
+    qxd.qxd_nn_set_skip(net, 0.27)
+    r = sg.spinor(W["source_seed"] + 9, o.V)
+    r[o.parity() == 1] = 0
+    out = lat.field(qxd.F32)
+    rin = lat.pack(to_dev(r), qxd.F32)[:12 * lat.Ve].clone()
+    qxd.qxd_nn_apply(lat.h, net, out, rin)
+    again = lat.field(qxd.F32)
+    qxd.qxd_nn_apply(lat.h, net, again, rin)
+    full_out = lat.field(qxd.F32, full=True)
+    full_out[:12 * lat.Ve] = out
+    got = lat.unpack(full_out, qxd.F32)[torch.from_numpy(sites).cuda()].cpu().numpy()
+    same = bool(torch.equal(out, again))
+    qxd.qxd_nn_destroy(net)
+    r32 = r.astype(np.complex64).astype(np.complex128)
+    n = np.linalg.norm(r32)
+    want = n * onn.forward_sites(o, ws, r32 / n, sites, 0.27, nb=nb, bf16=True)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    rms = np.linalg.norm(want) / np.sqrt(len(sites))
+    worst = np.linalg.norm((got - want).reshape(len(sites), -1), axis=1).max() / rms
+    print("uneven split: %d sampled sites, rel err %.2e, worst site %.2e of the rms" % (len(sites), err, worst))
+    assert same  # a second application gives the same bits
     assert err < 2e-3
     assert worst < 5e-3
