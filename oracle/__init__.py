@@ -105,6 +105,13 @@ class Oracle:
         self._lib.or_extents(self.h, le.ctypes.data)
         self.Le = tuple(int(v) for v in le)
         self.Vphys = self.L[0] * self.L[1] * self.L[2] * self.L[3]
+        self._has_gauge = False
+        self._has_flavour = False
+
+    def _need(self, flavour=True):
+        # the C side dereferences the links (and the flavour's tables) unchecked
+        if not self._has_gauge or (flavour and not self._has_flavour):
+            raise RuntimeError("oracle: set the gauge field%s first" % (" and the flavour" if flavour else ""))
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -145,22 +152,27 @@ class Oracle:
         A = _c(A, np.float64)
         assert U.shape == (4, self.Vphys, 3, 3) and A.shape == (4, self.Vphys)
         self._lib.or_set_gauge_physical(self.h, U.ctypes.data, A.ctypes.data)
+        self._has_gauge = True
 
     def set_gauge_extended(self, U, A):
         U = _c(U, np.complex128)
         A = _c(A, np.float64)
         assert U.shape == (4, self.V, 3, 3) and A.shape == (4, self.V)
         self._lib.or_set_gauge_extended(self.h, U.ctypes.data, A.ctypes.data)
+        self._has_gauge = True
 
     def gauge_extended(self):
+        self._need(flavour=False)
         U = np.empty((4, self.V, 3, 3), dtype=np.complex128)
         A = np.empty((4, self.V), dtype=np.float64)
         self._lib.or_get_gauge_extended(self.h, U.ctypes.data, A.ctypes.data)
         return U, A
 
     def set_flavour(self, qhat, invqel, kappa, su3csw, u1csw, cache=True, blocks=None):
+        self._need(flavour=False)
         self._lib.or_set_flavour(self.h, int(qhat), float(invqel), float(kappa), float(su3csw),
                                  float(u1csw), int(bool(cache)))
+        self._has_flavour = True
         if blocks if blocks is not None else cache:
             self._lib.or_cache_blocks(self.h)
 
@@ -171,28 +183,33 @@ class Oracle:
         return psi
 
     def field_tensors(self, site: int):
+        self._need(flavour=False)
         F = np.empty((4, 4, 3, 3), dtype=np.complex128)
         A = np.empty((4, 4), dtype=np.complex128)
         self._lib.or_field_tensors(self.h, int(site), F.ctypes.data, A.ctypes.data)
         return F, A
 
     def sw_site(self, site: int):
+        self._need()
         M = np.empty((12, 12), dtype=np.complex128)
         self._lib.or_sw_site(self.h, int(site), M.ctypes.data)
         return M
 
     def site_block(self, site: int):
+        self._need()
         M = np.empty((12, 12), dtype=np.complex128)
         self._lib.or_site_block(self.h, int(site), M.ctypes.data)
         return M
 
     def dirac(self, psi):
+        self._need()
         psi = self._spinor(psi)
         out = np.empty_like(psi)
         self._lib.or_dirac(self.h, psi.ctypes.data, out.ctypes.data)
         return out
 
     def dirac_sites(self, psi, sites):
+        self._need()
         psi = self._spinor(psi)
         s = _c(sites, np.int64)
         out = np.empty((s.size, 4, 3), dtype=np.complex128)
@@ -200,12 +217,14 @@ class Oracle:
         return out
 
     def schur(self, psi, dagger=False):
+        self._need()
         psi = self._spinor(psi)
         out = np.empty_like(psi)
         self._lib.or_schur(self.h, psi.ctypes.data, out.ctypes.data, int(bool(dagger)))
         return out
 
     def schur_sites(self, psi, sites, dagger=False):
+        self._need()
         psi = self._spinor(psi)
         s = _c(sites, np.int64)
         out = np.empty((s.size, 4, 3), dtype=np.complex128)
@@ -214,15 +233,18 @@ class Oracle:
         return out
 
     def min_block_pivot(self) -> float:
+        self._need()
         return float(self._lib.or_min_block_pivot(self.h))
 
     def eo_source(self, b):
+        self._need()
         b = self._spinor(b)
         out = np.empty_like(b)
         self._lib.or_eo_source(self.h, b.ctypes.data, out.ctypes.data)
         return out
 
     def eo_reconstruct(self, xe, b):
+        self._need()
         xe = self._spinor(xe)
         b = self._spinor(b)
         out = np.empty_like(b)
@@ -230,6 +252,7 @@ class Oracle:
         return out
 
     def cg(self, bhat, tol_abs, nmx=100000):
+        self._need()
         bhat = self._spinor(bhat)
         x = np.empty_like(bhat)
         res = ctypes.c_double(0.0)

@@ -452,3 +452,21 @@ def test_gauge_covariance_through_physical_fields(L, cstar):
     o2.set_flavour(**FU)
     psi = sg.spinor(4, o.V)
     assert rel(o2.dirac(rotate_spinor(g, psi)), rotate_spinor(g, o.dirac(psi))) < 1e-13
+
+
+def test_operator_calls_before_the_gauge_field_raise():
+    """The C side reads the links and the flavour's tables unchecked: the
+    wrapper refuses operator calls until both have been set."""
+    o = oracle.Oracle((4, 2, 2, 2), 1)
+    psi = np.zeros((o.V, 4, 3), dtype=np.complex128)
+    with pytest.raises(RuntimeError):
+        o.schur(psi)
+    with pytest.raises(RuntimeError):
+        o.set_flavour(-2, 1.0 / 6.0, 0.13, 1.0, 0.5)
+    U = sg.gauge_su3(1, 0.2, o.Vphys)
+    A = sg.gauge_u1(1, 0.3, o.Vphys)
+    o.set_gauge_physical(U, A)
+    with pytest.raises(RuntimeError):
+        o.dirac(psi)
+    o.set_flavour(-2, 1.0 / 6.0, 0.13, 1.0, 0.5)
+    assert np.all(o.schur(psi) == 0)
