@@ -13,14 +13,18 @@ The same check on the 36 x 8 x 16 x 32 physical lattice (extended 36 x 16 x
 them three blocks and the others two, so the halo loaded for a next block,
 the last block of a workgroup and the uneven split all occur (measured 1.8e-4
 in norm, 7.1e-4 for the worst site), and a second application gives the same
-bits."""
+bits.  On the 36 x 8 x 8 x 32 lattice (288 blocks, four workgroups walking
+two) the loss and the weight gradients of one pair under the residual loss,
+through the backward kernels, against the oracle's bfloat16 mode: the bars of
+the small-lattice tests (loss 1e-4, gradients 1e-2 in norm; measured 7.6e-7
+and 1.3e-3, 7.6e-5, 3.4e-5 for layers 1-3)."""
 import numpy as np
 import pytest
 
 import oracle
 import synthgen as sg
 from oracle import nn as onn
-from tests.gpu_common import to_dev
+from tests.gpu_common import make_pair, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -133,3 +137,33 @@ def test_network_apply_uneven_block_split_sampled(ragged):
     assert same  # a second application gives the same bits
     assert err < 2e-3
     assert worst < 5e-3
+
+
+def test_network_loss_and_gradients_with_next_block_halo():
+    L, cstar = (36, 8, 8, 32), 3
+    o, lat, _ = make_pair(L, cstar, sg.FLAVOURS["d"], sigma=0.2, su1=0.3, seed=37)
+    ws = init_weights(8)
+    net = qxd.qxd_nn_create(lat.h)
+    qxd.qxd_nn_set_weights(net, np.concatenate([w.reshape(-1) for w in ws]).astype(np.float32))
+    qxd.qxd_nn_set_skip(net, 0.27)
+    par = o.parity()
+    r = sg.spinor(71, o.V)
+    e = sg.spinor(72, o.V)
+    r[par == 1] = 0
+    e[par == 1] = 0
+    R = lat.pack(to_dev(r), qxd.F32)[:12 * lat.Ve].clone()
+    E = lat.pack(to_dev(e), qxd.F32)[:12 * lat.Ve].clone()
+    loss, grad = qxd.qxd_nn_loss_grad(lat.h, net, R, E, 1, 1)
+    qxd.qxd_nn_destroy(net)
+    lat.close()
+    f32 = lambda a: a.astype(np.complex64).astype(np.complex128)  # noqa: E731
+    L0, g0 = onn.loss_and_grad(o, ws, [f32(r)], [f32(e)], 1, 0.27, bf16=True)
+    print("loss gpu %.6f oracle %.6f" % (loss, L0))
+    assert abs(loss - L0) / L0 < 1e-4
+    off = 0
+    for k, (ci, co) in enumerate(SHAPES):
+        n = 81 * co * ci
+        err = np.linalg.norm(grad[off:off + n].reshape(81, co, ci) - g0[k]) / np.linalg.norm(g0[k])
+        off += n
+        print("layer %d grad rel err %.2e" % (k + 1, err))
+        assert err < 1e-2
