@@ -54,12 +54,17 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_link_cast32(int64_t n, const doub
   double2 v = V64[t];
   V32[t] = make_float2((float)v.x, (float)v.y);
 }
-__global__ __launch_bounds__(QXD_BLOCK) void k_link_cast16(int64_t n, const double2* __restrict__ V64,
+// entry k of link (parity, mu, h) goes to word 4 h + k (k < 4), 4 Ve + 4 h + k - 4
+// (k < 8) or 8 Ve + h (k = 8) of the 9 Ve words of (parity, mu)
+__global__ __launch_bounds__(QXD_BLOCK) void k_link_cast16(int64_t n, int64_t Ve, const double2* __restrict__ V64,
                                                             uint32_t* __restrict__ V16) {
   int64_t t = (int64_t)blockIdx.x * QXD_BLOCK + threadIdx.x;
   if (t >= n) return;
+  const int64_t h = t % Ve, r = t / Ve;
+  const int64_t k = r % 9, pm = r / 9;
+  const int64_t dst = pm * 9 * Ve + (k < 4 ? 4 * h + k : k < 8 ? 4 * Ve + 4 * h + (k - 4) : 8 * Ve + h);
   double2 v = V64[t];
-  V16[t] = pack_bf16x2((float)v.x, (float)v.y);
+  V16[dst] = pack_bf16x2((float)v.x, (float)v.y);
 }
 
 qxd_status ensure_link_copies(qxd_handle* h, unsigned which, hipStream_t s) {
@@ -74,7 +79,8 @@ qxd_status ensure_link_copies(qxd_handle* h, unsigned which, hipStream_t s) {
   if ((which & CP_V16) && !(h->copies & CP_V16)) {
     if (!h->has_flavour) return QXD_ESTATE;
     if (!h->V16 && !dev_alloc(&h->V16, n * sizeof(uint32_t))) return QXD_ENOMEM;
-    hipLaunchKernelGGL(k_link_cast16, dim3(div_up(n, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, n, h->V64, h->V16);
+    hipLaunchKernelGGL(k_link_cast16, dim3(div_up(n, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, n, (int64_t)h->Ve, h->V64,
+                       h->V16);
     QXD_HIP(hipGetLastError());
     h->copies |= CP_V16;
   }

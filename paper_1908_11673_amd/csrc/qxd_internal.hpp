@@ -4,7 +4,8 @@
 //   spinor half field  F64  double2 [12][Ve]      component c = 3 spin + colour
 //                      F32  float4  [6][Ve]       components (2j, 2j+1)
 //                      BF16 uint4   [3][Ve]       components 4j..4j+3, bf16 (re, im)
-//   links V = U z^qhat  [parity][mu][9][Ve] of double2 / float2 / bf16x2 (uint32),
+//   links V = U z^qhat  [parity][mu][9][Ve] of double2 / float2; bf16x2 (uint32) regrouped per
+//                       (parity, mu) as [4 entries][Ve] + [4 entries][Ve] + [1 entry][Ve] (see lk_load),
 //                       row-major colour matrix, entry k = 3 row + col
 //   clover blocks       [36][Ve] double2 or [18][Ve] float4 per parity: two
 //                       Hermitian 6x6 blocks (upper, lower chirality), each 36
@@ -282,12 +283,24 @@ __device__ inline void lk_load(const float2* __restrict__ V, size_t Ve, int mu, 
     u[k] = mk(v.x, v.y);
   }
 }
+// bf16 links: the 9 Ve words of (parity, mu) hold entries 0..3 of every link
+// as one 16-byte word per h, then entries 4..7 likewise, then entry 8 as a
+// 4-byte word per h: one link in three loads instead of nine
+typedef uint32_t nt_u4 __attribute__((ext_vector_type(4)));
 __device__ inline void lk_load(const uint32_t* __restrict__ V, size_t Ve, int mu, int h, cx<float> u[9]) {
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    uint32_t v = ld_stream(&V[(mu * 9 + k) * Ve + h]);
-    u[k] = mk(bf16lo(v), bf16hi(v));
-  }
+  const uint32_t* base = V + (size_t)mu * 9 * Ve;
+  const nt_u4 a = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(base) + h);
+  const nt_u4 b = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(base + 4 * Ve) + h);
+  const uint32_t c = ld_stream(base + 8 * Ve + h);
+  u[0] = mk(bf16lo(a.x), bf16hi(a.x));
+  u[1] = mk(bf16lo(a.y), bf16hi(a.y));
+  u[2] = mk(bf16lo(a.z), bf16hi(a.z));
+  u[3] = mk(bf16lo(a.w), bf16hi(a.w));
+  u[4] = mk(bf16lo(b.x), bf16hi(b.x));
+  u[5] = mk(bf16lo(b.y), bf16hi(b.y));
+  u[6] = mk(bf16lo(b.z), bf16hi(b.z));
+  u[7] = mk(bf16lo(b.w), bf16hi(b.w));
+  u[8] = mk(bf16lo(c), bf16hi(c));
 }
 
 // clover storage: two packed Hermitian 6x6 blocks (72 reals)
