@@ -47,12 +47,17 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_make_links(Geo g, PhysExt pe, con
 }
 
 // FP32 and bf16 copies of the links (each entry rounded to FP32, then to bf16)
-__global__ __launch_bounds__(QXD_BLOCK) void k_link_cast32(int64_t n, const double2* __restrict__ V64,
+// entry k of link (parity, mu, h) goes to float2 lk32_index(Ve, k, h) of the
+// 9 Ve of (parity, mu)
+__global__ __launch_bounds__(QXD_BLOCK) void k_link_cast32(int64_t n, int64_t Ve, const double2* __restrict__ V64,
                                                             float2* __restrict__ V32) {
   int64_t t = (int64_t)blockIdx.x * QXD_BLOCK + threadIdx.x;
   if (t >= n) return;
+  const int64_t h = t % Ve, r = t / Ve;
+  const int k = (int)(r % 9);
+  const int64_t pm = r / 9;
   double2 v = V64[t];
-  V32[t] = make_float2((float)v.x, (float)v.y);
+  V32[pm * 9 * Ve + lk32_index(Ve, k, h)] = make_float2((float)v.x, (float)v.y);
 }
 // entry k of link (parity, mu, h) goes to word 4 h + k (k < 4), 4 Ve + 4 h + k - 4
 // (k < 8) or 8 Ve + h (k = 8) of the 9 Ve words of (parity, mu)
@@ -72,7 +77,8 @@ qxd_status ensure_link_copies(qxd_handle* h, unsigned which, hipStream_t s) {
   if ((which & CP_V32) && !(h->copies & CP_V32)) {
     if (!h->has_flavour) return QXD_ESTATE;
     if (!h->V32 && !dev_alloc(&h->V32, n * sizeof(float2))) return QXD_ENOMEM;
-    hipLaunchKernelGGL(k_link_cast32, dim3(div_up(n, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, n, h->V64, h->V32);
+    hipLaunchKernelGGL(k_link_cast32, dim3(div_up(n, QXD_BLOCK)), dim3(QXD_BLOCK), 0, s, n, (int64_t)h->Ve, h->V64,
+                       h->V32);
     QXD_HIP(hipGetLastError());
     h->copies |= CP_V32;
   }

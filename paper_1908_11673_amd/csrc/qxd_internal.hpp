@@ -4,8 +4,8 @@
 //   spinor half field  F64  double2 [12][Ve]      component c = 3 spin + colour
 //                      F32  float4  [6][Ve]       components (2j, 2j+1)
 //                      BF16 uint4   [3][Ve]       components 4j..4j+3, bf16 (re, im)
-//   links V = U z^qhat  [parity][mu][9][Ve] of double2 / float2; bf16x2 (uint32) regrouped per
-//                       (parity, mu) as [4 entries][Ve] + [4 entries][Ve] + [1 entry][Ve] (see lk_load),
+//   links V = U z^qhat  [parity][mu][9][Ve] of double2; float2 and bf16x2 (uint32) regrouped per
+//                       (parity, mu) into 16-byte words of 2 or 4 entries per site (see lk_load),
 //                       row-major colour matrix, entry k = 3 row + col
 //   clover blocks       [36][Ve] double2 or [18][Ve] float4 per parity: two
 //                       Hermitian 6x6 blocks (upper, lower chirality), each 36
@@ -276,12 +276,22 @@ __device__ inline void lk_load(const double2* __restrict__ V, size_t Ve, int mu,
     u[k] = mk(v.x, v.y);
   }
 }
+// FP32 links: the 9 Ve float2 of (parity, mu) hold entries 2j, 2j + 1 of every
+// link as one 16-byte word per h in the j-th quarter of the first 8 Ve
+// (j < 4), then entry 8 as an 8-byte word per h: one link in five loads
+__device__ inline size_t lk32_index(size_t Ve, int k, size_t h) {
+  return k < 8 ? (size_t)(k >> 1) * 2 * Ve + 2 * h + (k & 1) : 8 * Ve + h;
+}
 __device__ inline void lk_load(const float2* __restrict__ V, size_t Ve, int mu, int h, cx<float> u[9]) {
+  const float2* base = V + (size_t)mu * 9 * Ve;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    float2 v = ld_stream(&V[(mu * 9 + k) * Ve + h]);
-    u[k] = mk(v.x, v.y);
+  for (int j = 0; j < 4; ++j) {
+    float4 v = ld_stream(reinterpret_cast<const float4*>(base + (size_t)j * 2 * Ve) + h);
+    u[2 * j] = mk(v.x, v.y);
+    u[2 * j + 1] = mk(v.z, v.w);
   }
+  float2 v = ld_stream(base + 8 * Ve + h);
+  u[8] = mk(v.x, v.y);
 }
 // bf16 links: the 9 Ve words of (parity, mu) hold entries 0..3 of every link
 // as one 16-byte word per h, then entries 4..7 likewise, then entry 8 as a

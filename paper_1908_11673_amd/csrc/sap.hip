@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kSapSites) void k_sap_pack(Geo g, SapGeo sb, const 
   float2* vb = sap_blk<36>(Vb, B);
   float4* cb = sap_blk<18>(Cb, B);
 #pragma unroll 4
-  for (int k = 0; k < 36; ++k) vb[k * kSapSites + t] = Vp[k * Ve + h];
+  for (int k = 0; k < 36; ++k) vb[k * kSapSites + t] = Vp[(size_t)(k / 9) * 9 * Ve + lk32_index(Ve, k % 9, h)];
 #pragma unroll 6
   for (int k = 0; k < 18; ++k) cb[k * kSapSites + t] = Hp[k * Ve + h];
   if (EO && p) {
