@@ -46,7 +46,9 @@ __global__ __launch_bounds__(QXD_BLOCK) void k_make_links(Geo g, PhysExt pe, con
   }
 }
 
-// FP32 and bf16 copies of the links (each entry rounded to FP32, then to bf16)
+// FP32 and bf16 copies of the links (each entry rounded to FP32, then to bf16),
+// regrouped so that a site's entries form 16-byte words; these stay aligned
+// because Ve is a multiple of 8 (every extent of the lattice is even)
 // entry k of link (parity, mu, h) goes to float2 lk32_index(Ve, k, h) of the
 // 9 Ve of (parity, mu)
 __global__ __launch_bounds__(QXD_BLOCK) void k_link_cast32(int64_t n, int64_t Ve, const double2* __restrict__ V64,
